@@ -1,0 +1,215 @@
+"""Benchmark of the ray-traced Gaussian renderer on one MI355X.
+
+A step is one pass of the whole hot path over the scene-scale workload
+(1M Gaussians, one 1920x1080 view): BVH rebuild (preprocess, Morton codes,
+radix sort, Karras link, refit), forward render, an L1 loss against a fixed
+target image, and the adjoint render producing gradients for all five
+parameter groups. Inputs are resident in HBM before the timed region.
+
+Prints one JSON line. `value` is forward+backward throughput in Mrays/s.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mrays/s fwd and fwd+bwd at 1M Gaussians, % HBM roofline, vs oracle error"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--kbuf", type=int, default=0)
+    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-rays", type=int, default=96)
+    ap.add_argument("--parity-rays", type=int, default=256)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the renderer shards over rays, but this build runs and reports "
+              "a single MI355X only (use --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from synthetic import workload
+    from synthetic.cameras import concat_rays
+    from paper_2501_19196_amd import renderer as R
+
+    t0 = time.time()
+    w = workload(args.workload)
+    sc = w["scene"]
+    o, d, views = concat_rays(w["cams"])
+    views = [tuple(int(x) for x in v) for v in views]
+    target_scene = w.get("target")
+    print(f"[bench] workload {w['name']}: {sc.n} Gaussians, {o.shape[0]} rays (setup {time.time() - t0:.1f}s)",
+          file=sys.stderr, flush=True)
+
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g = R.Gaussians(*(t(a) for a in sc.arrays()))
+    rays = R.Rays(t(o), t(d), views=views)
+    flags = R.Params().flags | (2 if args.persistent else 0)
+    p = R.Params(kbuf=args.kbuf, flags=flags)
+    nr = o.shape[0]
+    n = sc.n
+
+    # fixed target: the scene rendered with means jittered by N(0, 0.01)
+    from synthetic.scenes import jittered_target
+    tsc = target_scene or jittered_target(sc, seed=2, sigma=0.01)
+    tg = R.Gaussians(*(t(a) for a in tsc.arrays()))
+    tb = R.build_bvh(tg, p)
+    target, _ = R.render_fwd(tb, tg, rays, p, want_state=False)
+    del tb, tg
+
+    ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device=dev)
+    out = torch.empty((nr, 3), dtype=torch.float32, device=dev)
+    state = torch.empty((nr, 4), dtype=torch.float32, device=dev)
+    grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
+             torch.empty_like(g.opacity), torch.empty_like(g.rgb))
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    kt = {"build": [], "fwd": [], "bwd": []}
+
+    def step(record):
+        e = [ev() for _ in range(4)] if record else None
+        if record:
+            e[0].record()
+        bvh = R.build_bvh(g, p, workspace=ws)
+        if record:
+            e[1].record()
+        R.render_fwd(bvh, g, rays, p, out=out, state=state)
+        if record:
+            e[2].record()
+        grad = torch.sign(out - target) * (1.0 / (3.0 * nr))  # d/dout of mean L1
+        if record:
+            e[3].record()
+        R.render_bwd(bvh, g, rays, p, grad, state, grads=grads)
+        if record:
+            e4 = ev()
+            e4.record()
+            return (e[0], e[1], e[2], e[3], e4)
+        return None
+
+    def fwd_step():
+        bvh = R.build_bvh(g, p, workspace=ws)
+        R.render_fwd(bvh, g, rays, p, out=out, state=None)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    status = R.read_status(R.build_bvh(g, p, workspace=ws))
+    torch.cuda.synchronize()
+
+    # timed: forward + backward steps
+    recs = []
+    s0, s1 = ev(), ev()
+    torch.cuda.synchronize()
+    s0.record()
+    for _ in range(args.steps):
+        recs.append(step(True))
+    s1.record()
+    torch.cuda.synchronize()
+    ms_step = s0.elapsed_time(s1) / args.steps
+    for r in recs:
+        kt["build"].append(r[0].elapsed_time(r[1]))
+        kt["fwd"].append(r[1].elapsed_time(r[2]))
+        kt["bwd"].append(r[3].elapsed_time(r[4]))
+
+    # timed: forward-only steps (rebuild + render)
+    f0, f1 = ev(), ev()
+    torch.cuda.synchronize()
+    f0.record()
+    for _ in range(args.steps):
+        fwd_step()
+    f1.record()
+    torch.cuda.synchronize()
+    ms_fwd = f0.elapsed_time(f1) / args.steps
+
+    med = {k: float(np.median(v)) for k, v in kt.items()}
+    mrays_fb = nr / (ms_step * 1e-3) / 1e6
+    mrays_f = nr / (ms_fwd * 1e-3) / 1e6
+    mrays_render = nr / (med["fwd"] * 1e-3) / 1e6
+
+    # algorithmic (compulsory) bytes of the dominant kernel: the adjoint render reads every ray
+    # (origin, dir 24 B, grad 12 B, state 16 B), every Gaussian record, index and raw parameters it
+    # needs (64 + 4 + 4 + 16 + 12 B), every BVH node (64 B) once, and writes 56 B of gradient per Gaussian
+    bwd_bytes = nr * (24 + 12 + 16) + n * (64 + 4 + 4 + 16 + 12) + (n - 1) * 64 + n * 56
+    fwd_bytes = nr * (24 + 12 + 16) + n * (64 + 4 + 12) + (n - 1) * 64
+    dom = "bwd" if med["bwd"] >= med["fwd"] else "fwd"
+    dom_bytes = bwd_bytes if dom == "bwd" else fwd_bytes
+    achieved = dom_bytes / (med[dom] * 1e-3) / 1e9
+
+    # parity on a seeded sample of pixels against the FP64 oracle
+    err = None
+    cpu = None
+    try:
+        from oracle import oracle as O
+        f32 = lambda x: float(np.float32(x))
+        op = O.Params(Q=f32(p.Q), eps1=f32(p.eps1), max_hits=p.max_hits)
+        rng = np.random.default_rng(123)
+        if args.parity_rays > 0:
+            sel = np.sort(rng.choice(nr, args.parity_rays, replace=False))
+            ref, _, _ = O.render_fwd(sc, o[sel], d[sel], op)
+            res = O.compare_with_alternatives(out.cpu().numpy()[sel], ref, sc, o[sel], d[sel], op, tol=1e-4)
+            err = dict(max_abs_rgb=res["max_err"], within_1e4=res["within"], resolved=res["resolved"],
+                       unresolved=len(res["unresolved"]), sampled=int(args.parity_rays))
+        if not args.no_cpu_baseline:
+            sel = np.sort(rng.choice(nr, args.cpu_rays, replace=False))
+            gsel = (np.sign(out.cpu().numpy()[sel] - target.cpu().numpy()[sel]) / (3.0 * nr)).astype(np.float64)
+            c0 = time.time()
+            O.render_fwd(sc, o[sel], d[sel], op)
+            c1 = time.time()
+            O.render_bwd(sc, o[sel], d[sel], gsel, op)
+            c2 = time.time()
+            cores = O.lib().orc_max_threads()
+            cpu = dict(value=args.cpu_rays / (c2 - c0) / 1e6, unit="Mrays/s", cores=int(cores), kind="oracle",
+                       sample=f"{args.cpu_rays} seeded pixels of the same view, forward + adjoint, brute force "
+                              f"over all {n} Gaussians (fwd {c1 - c0:.1f}s, bwd {c2 - c1:.1f}s)",
+                       fwd_value=args.cpu_rays / (c1 - c0) / 1e6)
+    except Exception as e:  # the oracle is optional on the GPU machine
+        print(f"[bench] oracle leg skipped: {e}", file=sys.stderr)
+
+    line = {
+        "metric": METRIC,
+        "value": round(mrays_fb, 3),
+        "unit": "Mrays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
+                   "kbuf": p.kbuf or 16, "persistent": bool(args.persistent), "step": "bvh+fwd+L1+bwd"},
+        "fwd_mrays_s": round(mrays_f, 3),
+        "render_only_fwd_mrays_s": round(mrays_render, 3),
+        "ms_fwd_step": round(ms_fwd, 4),
+        "kernel_ms_median": {k: round(v, 4) for k, v in med.items()},
+        "roofline": {"bound": "hbm", "kernel": f"render_{dom}", "achieved": round(achieved, 2),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
+                     "traffic": None, "algorithmic_bytes": int(dom_bytes)},
+        "device_status": status,
+        "parity": err,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,185 @@
+/*
+ * raysplats.h -- C ABI of the MI355X ray-traced Gaussian renderer.
+ *
+ * The library renders a scene of 3D (or flat) Gaussians by ray tracing, as in
+ * RaySplats (arXiv 2501.19196), and computes the adjoint of that rendering:
+ *
+ *   scene (Eq. 1-2)  G = {(N(m_i, Sigma_i), opacity_i, c_i)}, Sigma = R S S^T R^T,
+ *                    R from the quaternion q_i (App. A.6), S = diag(s_i)
+ *   hit (Sec. 3, Prop. 1)  ray r(t) = o + t d meets the confidence ellipsoid
+ *                    (x-m)^T Sigma^-1 (x-m) = Q; the hit depth is the nearer
+ *                    root t1; a ray misses when the line misses or t1 < t_min
+ *   alpha (Prop. 2)  alpha_i = opacity_i * exp(-h_i^2 / 2), h_i^2 the squared
+ *                    whitened distance between the line and the Gaussian centre
+ *   colour (Eq. 3)   hits sorted by (t1, Gaussian index) are composited front to
+ *                    back, C += T alpha c, T *= (1 - alpha); a ray stops after
+ *                    K_max hits or once T < eps1 (Sec. 3, "Color Aggregation");
+ *                    the output is C + T * background
+ *   adjoint (App. A.3-A.6)  gradients of sum_k <grad_rgb_k, C_k> with respect
+ *                    to every Gaussian parameter
+ *
+ * Conventions
+ *  - Plain C, no HIP or torch types. Every pointer documented as "device" is a
+ *    device (HBM) address; "host" pointers are read synchronously during the
+ *    call. `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *  - The caller owns every buffer, including the BVH workspace and the ray
+ *    state. The library keeps no per-call global state and never allocates
+ *    device memory.
+ *  - All calls are asynchronous on `stream`; argument validation is
+ *    synchronous and returns a negative status before anything is enqueued.
+ *  - Device-side faults (traversal stack overflow, non-finite inputs) are
+ *    recorded in a sticky status word inside the BVH workspace; read it with
+ *    rs_read_status.
+ *  - Parameters are the activated values: world-space scales (> 0), opacity
+ *    in [0, 1], raw quaternions (r, i, j, k), nonzero, not necessarily unit.
+ *    Gradients are with respect to these same values.
+ */
+#ifndef RAYSPLATS_H
+#define RAYSPLATS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ------------------------------------------------------------ status codes */
+enum {
+    RS_OK = 0,
+    RS_ERR_INVALID_ARG = -1,     /* a null pointer, negative size, bad flag or knob */
+    RS_ERR_WORKSPACE = -2,       /* workspace smaller than rs_bvh_workspace_bytes */
+    RS_ERR_HIP = -3,             /* a HIP runtime call failed (launch, copy) */
+    RS_ERR_BVH_MISMATCH = -4,    /* BVH built for another scene size or Q */
+    RS_ERR_STACK_OVERFLOW = -5,  /* device: traversal stack deeper than stack_depth */
+    RS_ERR_NONFINITE = -6,       /* device: a non-finite or out-of-range Gaussian parameter */
+    RS_ERR_UNSUPPORTED = -7      /* valid but unsupported combination (e.g. too many views) */
+};
+
+/* ------------------------------------------------------------------- flags */
+#define RS_BRUTE_FORCE  (1u << 0)  /* test every Gaussian against every ray (no BVH pruning) */
+#define RS_PERSISTENT   (1u << 1)  /* persistent launch: waves pop ray packets from a queue */
+#define RS_ZERO_COLOUR  (1u << 2)  /* take every Gaussian colour as 0: output = T * background
+                                      (transmittance / shadow rays) */
+
+#define RS_MAX_VIEWS 64
+
+/* Gaussian scene, structure of arrays, all device pointers, float32,
+ * row-major: mean[n][3], scale[n][3] (> 0), quat[n][4] (r, i, j, k),
+ * opacity[n] (in [0, 1]), rgb[n][3]. n <= 2^31 - 2. Read only. */
+typedef struct {
+    int64_t n;
+    const float *mean, *scale, *quat, *opacity, *rgb;
+} rs_gaussians;
+
+/* One camera's rays inside the ray array: rays [ray_offset, ray_offset + width*height)
+ * are an image of `width` x `height` pixels in row-major order. The renderer
+ * groups rays into 8x8 pixel tiles (one wavefront each) for coherence. */
+typedef struct {
+    int64_t ray_offset;
+    int32_t width, height;
+} rs_view;
+
+/* Rays r(t) = o + t d (device pointers, float32 [n][3]; d nonzero, need not be unit).
+ *  t_max  optional device [n]: a hit needs t1 < t_max[k] (NULL = +inf)
+ *  bg     optional device [n][3]: per-ray background (NULL = params->bg)
+ *  views  optional host table of n_views <= RS_MAX_VIEWS images tiling the rays
+ *         in order; n_views = 0 groups consecutive rays 64 at a time. */
+typedef struct {
+    int64_t n;
+    const float *origin, *dir;
+    const float *t_max;
+    const float *bg;
+    int32_t n_views;
+    const rs_view *views;
+} rs_rays;
+
+/* Renderer knobs. Q: ellipsoid quantile (Sec. 3; > 0). eps1: transmittance
+ * threshold (>= 0). t_min: minimum hit depth. max_hits: K_max (0 = unbounded).
+ * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 16).
+ * stack_depth: traversal stack entries (1..64; 0 = 64). packet_rays: rays per
+ * wavefront packet (64; 0 = 64). */
+typedef struct {
+    float Q, eps1, t_min;
+    int32_t max_hits;
+    float bg[3];
+    uint32_t flags;
+    int32_t kbuf;
+    int32_t stack_depth;
+    int32_t packet_rays;
+} rs_params;
+
+/* Gradient outputs (device, float32, same shapes as the inputs). Any pointer
+ * may be NULL to skip that group. Overwritten (the library zeroes them first). */
+typedef struct {
+    float *d_mean, *d_scale, *d_quat, *d_opacity, *d_rgb;
+} rs_grads;
+
+/* BVH descriptor: plain data naming sections of the caller's workspace. */
+typedef struct {
+    uint64_t opaque[16];
+} rs_bvh;
+
+/* Fill *p with the defaults: Q = 11.3449 (chi^2(3) 0.99 quantile), eps1 = 1e-4,
+ * t_min = 0, max_hits = 512, black background, no flags, automatic kbuf,
+ * stack depth and packet size. */
+void rs_default_params(rs_params *p);
+
+/* Device workspace needed to build and keep a BVH over n Gaussians. */
+size_t rs_bvh_workspace_bytes(int64_t n_gaussians);
+
+/* Per-ray state written by rs_render_fwd and read by rs_render_bwd
+ * (16 bytes per ray: composited colour and final transmittance). */
+size_t rs_ray_state_bytes(int64_t n_rays);
+
+/* Build the BVH (linear BVH over 30-bit Morton codes of the means, LDS radix
+ * sort, Karras radix-tree linking, bottom-up box refit). The paper traverses
+ * with a vendor ray-tracing API (Sec. 5); this structure replaces it.
+ *  g        scene (device arrays)
+ *  p        knobs; Q fixes the ellipsoid size the boxes bound
+ *  ws       device workspace of ws_bytes >= rs_bvh_workspace_bytes(g->n),
+ *           256-byte aligned; owned by the caller, must outlive every render
+ *           that uses *out
+ *  out      descriptor (host) to pass to the render calls
+ * Also resets the sticky status word. Returns RS_OK or a negative status. */
+int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_bytes, rs_bvh *out,
+                 void *stream);
+
+/* Forward render (Sec. 3 "Color Aggregation", Eq. 3, Props. 1-2).
+ *  bvh        from rs_build_bvh over the same scene size and Q
+ *  out_rgb    device float32 [rays->n][3], written
+ *  ray_state  device buffer of rs_ray_state_bytes(rays->n) bytes, 16-byte
+ *             aligned, written; needed by rs_render_bwd (may be NULL when no
+ *             backward pass follows) */
+int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                  float *out_rgb, void *ray_state, void *stream);
+
+/* Adjoint render (App. A.3-A.6): re-traverses every ray, recomputing its
+ * hits front to back instead of storing them, and accumulates
+ * d/dtheta sum_k <grad_rgb[k], C_k> into `out` with wave-aggregated float32
+ * atomics. Must use the same bvh, scene, rays and params as the forward call
+ * that wrote ray_state. grad_rgb: device float32 [rays->n][3]. */
+int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                  const float *grad_rgb, const void *ray_state, rs_grads *out, void *stream);
+
+/* Synchronise `stream` and return the sticky device status of this BVH's
+ * workspace (RS_OK, RS_ERR_STACK_OVERFLOW or RS_ERR_NONFINITE). */
+int rs_read_status(const rs_bvh *bvh, void *stream);
+
+/* Human-readable text of a status code (static string). */
+const char *rs_status_string(int code);
+
+/* Copy the built BVH to host memory for inspection (synchronises `stream`).
+ * Any pointer may be NULL. codes[n] (uint32, sorted Morton codes),
+ * perm[n] (int32, sorted position -> Gaussian index),
+ * child[n-1][2] (int32; >= 0 internal node, < 0 leaf ~position),
+ * boxes[n-1][2][6] (float32 child boxes lo.xyz, hi.xyz),
+ * leaf_boxes[n][6], bounds[6] (scene box of the means). */
+int rs_bvh_download(const rs_bvh *bvh, uint32_t *codes, int32_t *perm, int32_t *child, float *boxes,
+                    float *leaf_boxes, float *bounds, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RAYSPLATS_H */

@@ -68,6 +68,8 @@ def lib():
         L.orc_ray_alternatives.argtypes = [P, P, C.c_int64, P, C.c_double, C.c_double, C.c_double, C.c_int,
                                            C.c_int64, P]
         L.orc_ray_alternatives.restype = C.c_int64
+        L.orc_alternatives_batch.argtypes = [P, P, P, C.c_double, C.c_double, C.c_double, C.c_int, C.c_int64, P, P,
+                                             C.c_int]
         L.orc_morton_codes.argtypes = [C.c_int64, P, P, P, P]
         L.orc_sort_codes.argtypes = [C.c_int64, P, P, P]
         L.orc_radix_tree.argtypes = [C.c_int64, P, P, P]
@@ -180,6 +182,49 @@ def ray_alternatives(scene, origin, direction, k, params=None, dh=1e-5, dt=1e-6,
     if n < 0:
         return None
     return out[:min(n, cap)]
+
+
+def alternatives_batch(scene, origin, direction, params=None, dh=1e-4, dt=1e-5, dT=1e-3, max_events=3,
+                       t_max=None, bg=None, cap=16, threads=0):
+    """Per ray: (count[n], colours[n, cap, 3]); count -1 marks an unresolved ray."""
+    params = params or Params()
+    b = _Bound(scene, origin, direction, t_max, bg)
+    n = b.o.shape[0]
+    cnt = np.zeros(n, np.int64)
+    out = np.zeros((n, cap, 3))
+    p = params.c()
+    lib().orc_alternatives_batch(C.byref(b.sc), C.byref(b.rays), C.byref(p), float(dh), float(dt), float(dT),
+                                 int(max_events), int(cap), _ptr(cnt), _ptr(out), int(threads))
+    return cnt, out
+
+
+def compare_with_alternatives(gpu_rgb, ref_rgb, scene, origin, direction, params=None, tol=1e-4, t_max=None,
+                              bg=None, **win):
+    """Parity protocol: a ray passes when |gpu - oracle| <= tol per channel, or
+    when its colour is within tol of one of the oracle's rounding-level
+    alternatives. Returns a dict of counts and the worst error after the protocol."""
+    gpu = np.asarray(gpu_rgb, np.float64).reshape(-1, 3)
+    ref = np.asarray(ref_rgb, np.float64).reshape(-1, 3)
+    err = np.abs(gpu - ref).max(axis=1)
+    bad = np.nonzero(err > tol)[0]
+    resolved = 0
+    unresolved = []
+    worst = float(err[err <= tol].max()) if np.any(err <= tol) else 0.0
+    if len(bad):
+        o = np.asarray(origin, np.float32).reshape(-1, 3)[bad]
+        d = np.asarray(direction, np.float32).reshape(-1, 3)[bad]
+        tm = None if t_max is None else np.asarray(t_max, np.float64)[bad]
+        bgs = None if bg is None else np.asarray(bg, np.float64).reshape(-1, 3)[bad]
+        cnt, alts = alternatives_batch(scene, o, d, params, t_max=tm, bg=bgs, **win)
+        for j, k in enumerate(bad):
+            if cnt[j] > 0:
+                e = np.abs(alts[j, :min(cnt[j], alts.shape[1])] - gpu[k]).max(axis=1).min()
+                if e <= tol:
+                    resolved += 1
+                    continue
+            unresolved.append(int(k))
+    return dict(n=len(gpu), within=int(len(gpu) - len(bad)), resolved=resolved, unresolved=unresolved,
+                max_err=float(err.max()) if len(err) else 0.0, worst_ok=worst)
 
 
 def intersect(scene, i, o, d, Q=Q_DEFAULT, t_min=0.0):

@@ -707,3 +707,14 @@ int64_t orc_ray_alternatives(const orc_scene *sc, const orc_rays *r, int64_t k, 
     free(as);
     return result;
 }
+
+/* orc_ray_alternatives for many rays at once (OpenMP over rays). out_n[k] is
+ * the count for ray k (or -1); out_rgb is [n][cap][3]. */
+void orc_alternatives_batch(const orc_scene *sc, const orc_rays *r, const orc_params *p, double dh, double dt,
+                            double dT, int max_events, int64_t cap, int64_t *out_n, double *out_rgb, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t k = 0; k < r->n; ++k)
+        out_n[k] = orc_ray_alternatives(sc, r, k, p, dh, dt, dT, max_events, cap, out_rgb + 3 * cap * k);
+}

@@ -1,0 +1,106 @@
+"""ctypes view of the C ABI declared in include/raysplats.h.
+
+Argument marshalling only: every step of the rendering runs in librs.so.
+Loading fails loudly when the library has not been built.
+"""
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librs.so")
+
+RS_OK = 0
+RS_ERR_INVALID_ARG = -1
+RS_ERR_WORKSPACE = -2
+RS_ERR_HIP = -3
+RS_ERR_BVH_MISMATCH = -4
+RS_ERR_STACK_OVERFLOW = -5
+RS_ERR_NONFINITE = -6
+RS_ERR_UNSUPPORTED = -7
+
+RS_BRUTE_FORCE = 1 << 0
+RS_PERSISTENT = 1 << 1
+RS_ZERO_COLOUR = 1 << 2
+RS_MAX_VIEWS = 64
+
+# Every symbol include/raysplats.h declares.
+EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", "rs_build_bvh", "rs_render_fwd",
+           "rs_render_bwd", "rs_read_status", "rs_status_string", "rs_bvh_download")
+
+
+class rs_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int64), ("mean", C.c_void_p), ("scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity", C.c_void_p), ("rgb", C.c_void_p)]
+
+
+class rs_view(C.Structure):
+    _fields_ = [("ray_offset", C.c_int64), ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class rs_rays(C.Structure):
+    _fields_ = [("n", C.c_int64), ("origin", C.c_void_p), ("dir", C.c_void_p), ("t_max", C.c_void_p),
+                ("bg", C.c_void_p), ("n_views", C.c_int32), ("views", C.POINTER(rs_view))]
+
+
+class rs_params(C.Structure):
+    _fields_ = [("Q", C.c_float), ("eps1", C.c_float), ("t_min", C.c_float), ("max_hits", C.c_int32),
+                ("bg", C.c_float * 3), ("flags", C.c_uint32), ("kbuf", C.c_int32), ("stack_depth", C.c_int32),
+                ("packet_rays", C.c_int32)]
+
+
+class rs_grads(C.Structure):
+    _fields_ = [("d_mean", C.c_void_p), ("d_scale", C.c_void_p), ("d_quat", C.c_void_p),
+                ("d_opacity", C.c_void_p), ("d_rgb", C.c_void_p)]
+
+
+class rs_bvh(C.Structure):
+    _fields_ = [("opaque", C.c_uint64 * 16)]
+
+
+class RaySplatsError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load librs.so (built by paper_2501_19196_amd.build). Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RaySplatsError(f"{LIB_PATH} is missing: build the HIP library first "
+                             "(python -m paper_2501_19196_amd.build)")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.rs_default_params.argtypes = [C.POINTER(rs_params)]
+    L.rs_default_params.restype = None
+    L.rs_bvh_workspace_bytes.argtypes = [C.c_int64]
+    L.rs_bvh_workspace_bytes.restype = C.c_size_t
+    L.rs_ray_state_bytes.argtypes = [C.c_int64]
+    L.rs_ray_state_bytes.restype = C.c_size_t
+    L.rs_build_bvh.argtypes = [C.POINTER(rs_gaussians), C.POINTER(rs_params), P, C.c_size_t, C.POINTER(rs_bvh), P]
+    L.rs_build_bvh.restype = C.c_int
+    L.rs_render_fwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_rays), C.POINTER(rs_params),
+                                P, P, P]
+    L.rs_render_fwd.restype = C.c_int
+    L.rs_render_bwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_rays), C.POINTER(rs_params),
+                                P, P, C.POINTER(rs_grads), P]
+    L.rs_render_bwd.restype = C.c_int
+    L.rs_read_status.argtypes = [C.POINTER(rs_bvh), P]
+    L.rs_read_status.restype = C.c_int
+    L.rs_status_string.argtypes = [C.c_int]
+    L.rs_status_string.restype = C.c_char_p
+    L.rs_bvh_download.argtypes = [C.POINTER(rs_bvh), P, P, P, P, P, P, P]
+    L.rs_bvh_download.restype = C.c_int
+    _lib = L
+    return L
+
+
+def check(code, what):
+    if code != RS_OK:
+        msg = lib().rs_status_string(code).decode()
+        raise RaySplatsError(f"{what} failed: {msg} ({code})")
+    return code

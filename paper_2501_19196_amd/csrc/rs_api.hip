@@ -1,0 +1,210 @@
+// C ABI entry points: argument validation, workspace sizing and dispatch to
+// the build and render launchers.
+#include <string.h>
+
+#include "rs_internal.h"
+
+namespace rs {
+int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st);
+int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
+                  void *state, const float *grad, const rs_grads *grads, hipStream_t st);
+}  // namespace rs
+
+using namespace rs;
+
+static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+static int check_gaussians(const rs_gaussians *g)
+{
+    if (!g || g->n < 0 || g->n > 0x7ffffffeLL) return RS_ERR_INVALID_ARG;
+    if (g->n > 0 && (!g->mean || !g->scale || !g->quat || !g->opacity || !g->rgb)) return RS_ERR_INVALID_ARG;
+    if (g->n > 0 && !aligned(g->quat, 16)) return RS_ERR_INVALID_ARG;
+    return RS_OK;
+}
+
+static int check_params(const rs_params *p)
+{
+    if (!p) return RS_ERR_INVALID_ARG;
+    if (!(p->Q > 0.0f) || !(p->eps1 >= 0.0f) || p->max_hits < 0 || !(p->t_min == p->t_min)) return RS_ERR_INVALID_ARG;
+    if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32) return RS_ERR_INVALID_ARG;
+    if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
+    if (p->packet_rays != 0 && p->packet_rays != 64) return RS_ERR_INVALID_ARG;
+    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR)) return RS_ERR_INVALID_ARG;
+    return RS_OK;
+}
+
+static int check_rays(const rs_rays *r)
+{
+    if (!r || r->n < 0) return RS_ERR_INVALID_ARG;
+    if (r->n > 0 && (!r->origin || !r->dir)) return RS_ERR_INVALID_ARG;
+    if (r->n_views < 0) return RS_ERR_INVALID_ARG;
+    if (r->n_views > RS_MAX_VIEWS) return RS_ERR_UNSUPPORTED;
+    if (r->n_views > 0) {
+        if (!r->views) return RS_ERR_INVALID_ARG;
+        int64_t expect = 0;
+        for (int v = 0; v < r->n_views; ++v) {
+            const rs_view &V = r->views[v];
+            if (V.width <= 0 || V.height <= 0 || V.ray_offset != expect) return RS_ERR_INVALID_ARG;
+            expect += int64_t(V.width) * V.height;
+        }
+        if (expect != r->n) return RS_ERR_INVALID_ARG;
+    }
+    return RS_OK;
+}
+
+static int check_bvh(const rs_bvh *b, const rs_gaussians *g, const rs_params *p, BvhDesc &D)
+{
+    if (!b) return RS_ERR_INVALID_ARG;
+    memcpy(&D, b, sizeof(D));
+    if (D.magic != kMagic || !D.ws) return RS_ERR_INVALID_ARG;
+    if (D.n != g->n || D.Q != p->Q) return RS_ERR_BVH_MISMATCH;
+    return RS_OK;
+}
+
+extern "C" {
+
+void rs_default_params(rs_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->Q = 11.3449f;
+    p->eps1 = 1e-4f;
+    p->t_min = 0.0f;
+    p->max_hits = 512;
+}
+
+size_t rs_bvh_workspace_bytes(int64_t n_gaussians)
+{
+    if (n_gaussians < 0) return 0;
+    return make_layout(n_gaussians).total;
+}
+
+size_t rs_ray_state_bytes(int64_t n_rays) { return n_rays > 0 ? size_t(n_rays) * 16 : 0; }
+
+int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_bytes, rs_bvh *out, void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if (!ws || !out || !aligned(ws, 256)) return RS_ERR_INVALID_ARG;
+    if (ws_bytes < make_layout(g->n).total) return RS_ERR_WORKSPACE;
+    e = launch_build(g, p->Q, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+    if (e) return e;
+    BvhDesc D{};
+    D.magic = kMagic;
+    D.n = g->n;
+    D.Q = p->Q;
+    D.root = g->n >= 2 ? 0 : ~0;
+    D.ws = static_cast<char *>(ws);
+    D.ws_bytes = ws_bytes;
+    memset(out, 0, sizeof(*out));
+    memcpy(out, &D, sizeof(D));
+    return RS_OK;
+}
+
+int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
+                  void *ray_state, void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if ((e = check_rays(rays))) return e;
+    BvhDesc D;
+    if ((e = check_bvh(bvh, g, p, D))) return e;
+    if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    return launch_render(D, g, rays, p, out_rgb, ray_state, nullptr, nullptr, static_cast<hipStream_t>(stream));
+}
+
+int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                  const float *grad_rgb, const void *ray_state, rs_grads *out, void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if ((e = check_rays(rays))) return e;
+    BvhDesc D;
+    if ((e = check_bvh(bvh, g, p, D))) return e;
+    if (!out) return RS_ERR_INVALID_ARG;
+    if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, 16))) return RS_ERR_INVALID_ARG;
+    return launch_render(D, g, rays, p, nullptr, const_cast<void *>(ray_state), grad_rgb, out,
+                         static_cast<hipStream_t>(stream));
+}
+
+int rs_read_status(const rs_bvh *bvh, void *stream)
+{
+    if (!bvh) return RS_ERR_INVALID_ARG;
+    BvhDesc D;
+    memcpy(&D, bvh, sizeof(D));
+    if (D.magic != kMagic || !D.ws) return RS_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(st) != hipSuccess) return RS_ERR_HIP;
+    int32_t s = 0;
+    Layout L = make_layout(D.n);
+    if (hipMemcpy(&s, D.ws + L.header, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+    if (s & kStatusStack) return RS_ERR_STACK_OVERFLOW;
+    if (s & kStatusNonfinite) return RS_ERR_NONFINITE;
+    return RS_OK;
+}
+
+const char *rs_status_string(int code)
+{
+    switch (code) {
+    case RS_OK: return "ok";
+    case RS_ERR_INVALID_ARG: return "invalid argument";
+    case RS_ERR_WORKSPACE: return "workspace too small";
+    case RS_ERR_HIP: return "HIP runtime error";
+    case RS_ERR_BVH_MISMATCH: return "BVH built for a different scene size or Q";
+    case RS_ERR_STACK_OVERFLOW: return "traversal stack overflow";
+    case RS_ERR_NONFINITE: return "non-finite or out-of-range Gaussian parameter";
+    case RS_ERR_UNSUPPORTED: return "unsupported configuration";
+    default: return "unknown status";
+    }
+}
+
+int rs_bvh_download(const rs_bvh *bvh, uint32_t *codes, int32_t *perm, int32_t *child, float *boxes,
+                    float *leaf_boxes, float *bounds, void *stream)
+{
+    if (!bvh) return RS_ERR_INVALID_ARG;
+    BvhDesc D;
+    memcpy(&D, bvh, sizeof(D));
+    if (D.magic != kMagic || !D.ws) return RS_ERR_INVALID_ARG;
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (hipStreamSynchronize(st) != hipSuccess) return RS_ERR_HIP;
+    Layout L = make_layout(D.n);
+    const int64_t n = D.n, ni = L.n_int;
+    auto cp = [&](void *dst, size_t off, size_t bytes) {
+        return (!dst || bytes == 0) ? hipSuccess : hipMemcpy(dst, D.ws + off, bytes, hipMemcpyDeviceToHost);
+    };
+    if (cp(codes, L.codes, size_t(n) * 4) != hipSuccess) return RS_ERR_HIP;
+    if (cp(perm, L.gidx, size_t(n) * 4) != hipSuccess) return RS_ERR_HIP;
+    if (cp(leaf_boxes, L.leaf_boxes, size_t(n) * 24) != hipSuccess) return RS_ERR_HIP;
+    if (bounds) {
+        WsHeader h;
+        if (hipMemcpy(&h, D.ws + L.header, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+        for (int k = 0; k < 6; ++k) {
+            uint32_t u = h.bounds[k];
+            uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+            memcpy(&bounds[k], &b, 4);
+        }
+    }
+    if ((child || boxes) && ni > 0) {
+        float *tmp = new float[size_t(ni) * 16];
+        if (hipMemcpy(tmp, D.ws + L.nodes, size_t(ni) * 64, hipMemcpyDeviceToHost) != hipSuccess) {
+            delete[] tmp;
+            return RS_ERR_HIP;
+        }
+        for (int64_t i = 0; i < ni; ++i) {
+            if (child) {
+                memcpy(&child[2 * i], &tmp[16 * i + 12], 4);
+                memcpy(&child[2 * i + 1], &tmp[16 * i + 13], 4);
+            }
+            if (boxes)
+                for (int k = 0; k < 12; ++k) boxes[12 * i + k] = tmp[16 * i + k];
+        }
+        delete[] tmp;
+    }
+    return RS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,406 @@
+// BVH build for gfx950: preprocessing of the Gaussians into 64-byte records,
+// 30-bit Morton codes, an LDS-tiled stable LSD radix sort, Karras radix-tree
+// linking and a bottom-up box refit.
+//
+// The paper finds the ellipsoids hit by a ray with a vendor ray-tracing API
+// (Sec. 3 "Intersection", Sec. 5); this linear BVH (Karras, HPG 2012) takes
+// its place. Leaf boxes bound the confidence ellipsoid (x-m)^T Sigma^-1 (x-m)
+// = Q with Sigma = R S S^T R^T (Eq. 2); R comes from the quaternion as in
+// App. A.6.
+#include <math.h>
+
+#include "rs_internal.h"
+
+namespace rs {
+
+// ------------------------------------------------------------- header init
+
+__global__ void k_init_header(WsHeader *h)
+{
+    if (threadIdx.x == 0) {
+        h->status = 0;
+        h->queue = 0;
+        for (int k = 0; k < 3; ++k) {
+            h->bounds[k] = 0xffffffffu;
+            h->bounds[3 + k] = 0u;
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) p[i] = v;
+}
+
+// ------------------------------------------------------------- scene bounds
+
+__global__ __launch_bounds__(256) void k_bounds(const float *__restrict__ mean, int64_t n, WsHeader *h)
+{
+    __shared__ uint32_t lo[3], hi[3];
+    if (threadIdx.x < 3) {
+        lo[threadIdx.x] = 0xffffffffu;
+        hi[threadIdx.x] = 0u;
+    }
+    __syncthreads();
+    uint32_t l[3] = {0xffffffffu, 0xffffffffu, 0xffffffffu}, u[3] = {0u, 0u, 0u};
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+        for (int k = 0; k < 3; ++k) {
+            uint32_t o = float_to_ordered(mean[3 * i + k]);
+            l[k] = min(l[k], o);
+            u[k] = max(u[k], o);
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        atomicMin(&lo[k], l[k]);
+        atomicMax(&hi[k], u[k]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) {
+        atomicMin(&h->bounds[threadIdx.x], lo[threadIdx.x]);
+        atomicMax(&h->bounds[3 + threadIdx.x], hi[threadIdx.x]);
+    }
+}
+
+// ------------------------------------------------------------------ Morton
+
+__device__ inline uint32_t spread10(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline bool finite3(float a, float b, float c) { return isfinite(a) && isfinite(b) && isfinite(c); }
+
+// Codes of the bit-exact spec: lo/hi the float32 min/max of the means,
+// scale = 1024 / (hi - lo) correctly rounded (0 on a flat axis),
+// q = min(uint((c - lo) * scale), 1023) without contraction, x in the top bit.
+__global__ __launch_bounds__(256) void k_morton(const float *__restrict__ mean, const float *__restrict__ scale,
+                                                const float *__restrict__ quat, const float *__restrict__ opacity,
+                                                const float *__restrict__ rgb, int64_t n, WsHeader *h,
+                                                uint32_t *__restrict__ codes, uint32_t *__restrict__ vals)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float lo[3], sc[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = ordered_to_float(h->bounds[k]);
+        float hi = ordered_to_float(h->bounds[3 + k]);
+        float ext = __fsub_rn(hi, lo[k]);
+        sc[k] = (hi == lo[k]) ? 0.0f : __fdiv_rn(1024.0f, ext);
+    }
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+        float v = __fmul_rn(__fsub_rn(mean[3 * i + k], lo[k]), sc[k]);
+        v = fminf(fmaxf(v, 0.0f), 1023.0f);  // also maps NaN to 0 (fmaxf returns the number)
+        uint32_t u = uint32_t(v);
+        q[k] = u > 1023u ? 1023u : u;
+    }
+    codes[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
+    vals[i] = uint32_t(i);
+    // input validation (sticky device status)
+    float s0 = scale[3 * i], s1 = scale[3 * i + 1], s2 = scale[3 * i + 2];
+    float q0 = quat[4 * i], q1 = quat[4 * i + 1], q2 = quat[4 * i + 2], q3 = quat[4 * i + 3];
+    float op = opacity[i];
+    bool ok = finite3(mean[3 * i], mean[3 * i + 1], mean[3 * i + 2]) && finite3(s0, s1, s2) && s0 > 0.0f &&
+              s1 > 0.0f && s2 > 0.0f && finite3(q0, q1, q2) && isfinite(q3) &&
+              (q0 != 0.0f || q1 != 0.0f || q2 != 0.0f || q3 != 0.0f) && op >= 0.0f && op <= 1.0f &&
+              finite3(rgb[3 * i], rgb[3 * i + 1], rgb[3 * i + 2]);
+    if (!ok) atomicOr(&h->status, kStatusNonfinite);
+}
+
+// -------------------------------------------------------------- radix sort
+
+__global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *__restrict__ keys, int64_t n, int shift,
+                                                          uint32_t *__restrict__ hist, int64_t nblocks)
+{
+    __shared__ uint32_t hs[256];
+    hs[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int c = 0; c < kSortItems; ++c) {
+        int64_t i = base + c * kSortBlock + threadIdx.x;
+        if (i < n) atomicAdd(&hs[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = hs[threadIdx.x];
+}
+
+// Exclusive scan of the digit-major histogram (one workgroup).
+__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t m)
+{
+    __shared__ uint32_t s[1024];
+    int t = threadIdx.x;
+    int64_t per = (m + 1023) / 1024;
+    int64_t b = t * per, e = min(b + per, m);
+    uint32_t sum = 0;
+    for (int64_t i = b; i < e; ++i) sum += hist[i];
+    s[t] = sum;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        uint32_t v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    uint32_t run = s[t] - sum;
+    for (int64_t i = b; i < e; ++i) {
+        uint32_t v = hist[i];
+        hist[i] = run;
+        run += v;
+    }
+}
+
+// Stable scatter: within a tile, keys are ranked among equal digits in input
+// order (wavefront match on the 8 digit bits, then a prefix over the four
+// wavefronts of the workgroup and over the chunks already placed).
+__global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *__restrict__ kin,
+                                                             const uint32_t *__restrict__ vin,
+                                                             uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                             int64_t n, int shift, const uint32_t *__restrict__ hist,
+                                                             int64_t nblocks)
+{
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t wcount[kSortBlock / kWave][256];
+    const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
+    run[t] = hist[int64_t(t) * nblocks + blockIdx.x];
+    const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int64_t base = int64_t(blockIdx.x) * kSortTile;
+    for (int c = 0; c < kSortItems; ++c) {
+        for (int ww = 0; ww < kSortBlock / kWave; ++ww) wcount[ww][t] = 0;
+        __syncthreads();
+        int64_t i = base + c * kSortBlock + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u, val = valid ? vin[i] : 0u;
+        uint32_t digit = (key >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int bit = 0; bit < 8; ++bit) {
+            bool on = (digit >> bit) & 1u;
+            uint64_t bal = __ballot(valid && on);
+            peers &= on ? bal : ~bal;
+        }
+        if (!valid) peers = 0;
+        uint32_t rank = __popcll(peers & lt_mask);
+        bool last = valid && ((peers >> lane) == 1ull);
+        if (last) wcount[w][digit] = __popcll(peers);
+        __syncthreads();
+        {
+            uint32_t acc = run[t];
+            for (int ww = 0; ww < kSortBlock / kWave; ++ww) {
+                uint32_t v = wcount[ww][t];
+                wcount[ww][t] = acc;
+                acc += v;
+            }
+            run[t] = acc;
+        }
+        __syncthreads();
+        if (valid) {
+            uint32_t pos = wcount[w][digit] + rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------------------------- records
+
+// Records and leaf boxes in sorted order; computed in FP64 from the float32
+// inputs and stored rounded (boxes rounded outward).
+__global__ __launch_bounds__(256) void k_records(const uint32_t *__restrict__ perm, const float *__restrict__ mean,
+                                                 const float *__restrict__ scale, const float *__restrict__ quat,
+                                                 const float *__restrict__ opacity, int64_t n, float Q,
+                                                 float4 *__restrict__ records, float *__restrict__ leaf_boxes,
+                                                 int32_t *__restrict__ inv)
+{
+    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    uint32_t i = perm[j];
+    double a = quat[4 * i], b = quat[4 * i + 1], c = quat[4 * i + 2], d = quat[4 * i + 3];
+    double nq = a * a + b * b + c * c + d * d;
+    if (!(nq > 0.0)) {
+        a = 1.0;
+        b = c = d = 0.0;
+        nq = 1.0;
+    }
+    double s = 2.0 / nq;
+    double R[3][3];
+    R[0][0] = 1.0 - s * (c * c + d * d);
+    R[0][1] = s * (b * c - a * d);
+    R[0][2] = s * (b * d + a * c);
+    R[1][0] = s * (b * c + a * d);
+    R[1][1] = 1.0 - s * (b * b + d * d);
+    R[1][2] = s * (c * d - a * b);
+    R[2][0] = s * (b * d - a * c);
+    R[2][1] = s * (c * d + a * b);
+    R[2][2] = 1.0 - s * (b * b + c * c);
+    double sc[3], m[3];
+    for (int k = 0; k < 3; ++k) {
+        sc[k] = scale[3 * i + k];
+        m[k] = mean[3 * i + k];
+    }
+    float4 r0, r1, r2, r3;
+    // row k of R^T is column k of R
+    r0 = make_float4(float(R[0][0]), float(R[1][0]), float(R[2][0]), float(R[0][1]));
+    r1 = make_float4(float(R[1][1]), float(R[2][1]), float(R[0][2]), float(R[1][2]));
+    r2 = make_float4(float(R[2][2]), float(1.0 / sc[0]), float(1.0 / sc[1]), float(1.0 / sc[2]));
+    r3 = make_float4(float(m[0]), float(m[1]), float(m[2]), opacity[i]);
+    records[4 * j + 0] = r0;
+    records[4 * j + 1] = r1;
+    records[4 * j + 2] = r2;
+    records[4 * j + 3] = r3;
+    // half extent along world axis k: sqrt(Q * sum_c (R_kc s_c)^2), padded
+    for (int k = 0; k < 3; ++k) {
+        double e2 = 0.0;
+        for (int cc = 0; cc < 3; ++cc) {
+            double v = R[k][cc] * sc[cc];
+            e2 += v * v;
+        }
+        double e = sqrt(double(Q) * e2) * (1.0 + 1e-5) + 1e-7 * (1.0 + fabs(m[k]));
+        leaf_boxes[6 * j + k] = __double2float_rd(m[k] - e);
+        leaf_boxes[6 * j + 3 + k] = __double2float_ru(m[k] + e);
+    }
+    inv[i] = int32_t(j);
+}
+
+// ------------------------------------------------------------ Karras link
+
+__device__ inline int delta(const uint32_t *__restrict__ codes, int64_t n, int64_t i, int64_t j)
+{
+    if (j < 0 || j >= n) return -1;
+    uint32_t a = codes[i], b = codes[j];
+    if (a == b) return 32 + __clz(uint32_t(i) ^ uint32_t(j));
+    return __clz(a ^ b);
+}
+
+__global__ __launch_bounds__(256) void k_karras(const uint32_t *__restrict__ codes, int64_t n,
+                                                float4 *__restrict__ nodes, int32_t *__restrict__ parent)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int dir = (delta(codes, n, i, i + 1) - delta(codes, n, i, i - 1)) >= 0 ? 1 : -1;
+    int dmin = delta(codes, n, i, i - dir);
+    int64_t lmax = 2;
+    while (delta(codes, n, i, i + lmax * dir) > dmin) lmax *= 2;
+    int64_t l = 0;
+    for (int64_t t = lmax / 2; t >= 1; t /= 2)
+        if (delta(codes, n, i, i + (l + t) * dir) > dmin) l += t;
+    int64_t j = i + l * dir;
+    int dnode = delta(codes, n, i, j);
+    int64_t s = 0;
+    int64_t t = l;
+    do {
+        t = (t + 1) / 2;
+        if (delta(codes, n, i, i + (s + t) * dir) > dnode) s += t;
+    } while (t > 1);
+    int64_t gamma = i + s * dir + (dir < 0 ? -1 : 0);
+    int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    int32_t left = (lo == gamma) ? ~int32_t(gamma) : int32_t(gamma);
+    int32_t right = (hi == gamma + 1) ? ~int32_t(gamma + 1) : int32_t(gamma + 1);
+    float4 n3;
+    n3.x = __int_as_float(left);
+    n3.y = __int_as_float(right);
+    n3.z = 0.0f;
+    n3.w = 0.0f;
+    nodes[4 * i + 3] = n3;
+    // parent links: leaves at [0, n), internal nodes at [n, 2n - 1)
+    parent[left < 0 ? ~left : n + left] = int32_t(i);
+    parent[right < 0 ? ~right : n + right] = int32_t(i);
+    if (i == 0) parent[n] = -1;
+}
+
+// --------------------------------------------------------------- box refit
+
+__device__ inline float ld_agent(const float *p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bottom-up union of child boxes: one thread per leaf climbs while it is the
+// second child to arrive at a node (atomic visit counter).
+__global__ __launch_bounds__(256) void k_refit(const float *__restrict__ leaf_boxes, const int32_t *__restrict__ parent,
+                                               float *nodes_f, uint32_t *visit, int64_t n, WsHeader *h)
+{
+    int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    float b[6];
+    for (int k = 0; k < 6; ++k) b[k] = leaf_boxes[6 * j + k];
+    int32_t ref = ~int32_t(j);
+    int32_t node = parent[j];
+    while (node >= 0) {
+        float *nf = nodes_f + 16 * int64_t(node);
+        int32_t left = __float_as_int(nf[12]);
+        int slot = (left == ref) ? 0 : 1;
+        // L box at floats [0, 6), R box at [6, 12)
+        for (int k = 0; k < 6; ++k) nf[6 * slot + k] = b[k];
+        __threadfence();
+        uint32_t old = atomicAdd(&visit[node], 1u);
+        if (old == 0) return;
+        __threadfence();
+        for (int k = 0; k < 3; ++k) {
+            b[k] = fminf(ld_agent(nf + k), ld_agent(nf + 6 + k));
+            b[3 + k] = fmaxf(ld_agent(nf + 3 + k), ld_agent(nf + 9 + k));
+        }
+        ref = node;
+        node = parent[n + node];
+    }
+    for (int k = 0; k < 6; ++k) h->root_box[k] = b[k];
+}
+
+// ------------------------------------------------------------------- host
+
+static inline int blocks_for(int64_t n, int threads) { return int((n + threads - 1) / threads); }
+
+int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
+{
+    const int64_t n = g->n;
+    Layout L = make_layout(n);
+    WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
+    k_init_header<<<1, 64, 0, st>>>(h);
+    if (n == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+    uint32_t *codes = reinterpret_cast<uint32_t *>(ws + L.codes);
+    uint32_t *vals = reinterpret_cast<uint32_t *>(ws + L.gidx);
+    uint32_t *kalt = reinterpret_cast<uint32_t *>(ws + L.keys_alt);
+    uint32_t *valt = reinterpret_cast<uint32_t *>(ws + L.vals_alt);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    float4 *records = reinterpret_cast<float4 *>(ws + L.records);
+    float4 *nodes = reinterpret_cast<float4 *>(ws + L.nodes);
+    float *leaf_boxes = reinterpret_cast<float *>(ws + L.leaf_boxes);
+    int32_t *inv = reinterpret_cast<int32_t *>(ws + L.inv);
+    int32_t *parent = reinterpret_cast<int32_t *>(ws + L.parent);
+    uint32_t *visit = reinterpret_cast<uint32_t *>(ws + L.visit);
+
+    int bgrid = blocks_for(n, 256);
+    k_bounds<<<bgrid < 1024 ? bgrid : 1024, 256, 0, st>>>(g->mean, n, h);
+    k_morton<<<bgrid, 256, 0, st>>>(g->mean, g->scale, g->quat, g->opacity, g->rgb, n, h, codes, vals);
+    // 4 passes of 8 bits: A -> B -> A -> B -> A
+    uint32_t *ka = codes, *va = vals, *kb = kalt, *vb = valt;
+    int64_t nb = L.sort_blocks;
+    for (int pass = 0; pass < 4; ++pass) {
+        int shift = 8 * pass;
+        k_sort_hist<<<int(nb), kSortBlock, 0, st>>>(ka, n, shift, hist, nb);
+        k_sort_scan<<<1, 1024, 0, st>>>(hist, 256 * nb);
+        k_sort_scatter<<<int(nb), kSortBlock, 0, st>>>(ka, va, kb, vb, n, shift, hist, nb);
+        uint32_t *t;
+        t = ka; ka = kb; kb = t;
+        t = va; va = vb; vb = t;
+    }
+    k_records<<<bgrid, 256, 0, st>>>(vals, g->mean, g->scale, g->quat, g->opacity, n, Q, records, leaf_boxes, inv);
+    if (n >= 2) {
+        k_fill_u32<<<blocks_for(L.n_int, 256) < 2048 ? blocks_for(L.n_int, 256) : 2048, 256, 0, st>>>(visit, L.n_int,
+                                                                                                       0u);
+        k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(codes, n, nodes, parent);
+        k_refit<<<bgrid, 256, 0, st>>>(leaf_boxes, parent, reinterpret_cast<float *>(nodes), visit, n, h);
+    } else {
+        (void)hipMemcpyAsync(h->root_box, leaf_boxes, 6 * sizeof(float), hipMemcpyDeviceToDevice, st);
+    }
+    return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+}  // namespace rs

@@ -1,0 +1,116 @@
+// Internal declarations of the MI355X renderer: workspace layout, the BVH
+// descriptor, record layouts and small device helpers shared by the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "raysplats.h"
+
+namespace rs {
+
+constexpr uint64_t kMagic = 0x5253425648495031ull;  // "RSBVHIP1"
+constexpr int kWave = 64;
+constexpr int kTile = 8;  // 8x8 pixel tiles, one wavefront each
+constexpr int kSortBlock = 256;
+constexpr int kSortItems = 8;  // keys per thread per sort tile
+constexpr int kSortTile = kSortBlock * kSortItems;
+
+// Device status bits (sticky, OR-ed by kernels).
+constexpr int kStatusStack = 1;
+constexpr int kStatusNonfinite = 2;
+
+// Gaussian record, one per sorted position (64 bytes, four float4):
+//   r0 = (RT00, RT01, RT02, RT10), r1 = (RT11, RT12, RT20, RT21),
+//   r2 = (RT22, 1/sx, 1/sy, 1/sz), r3 = (mx, my, mz, opacity)
+// RT = R^T, R the rotation of the normalised quaternion.
+// BVH node, one per internal node (64 bytes, four float4):
+//   n0 = (L.lo.x, L.lo.y, L.lo.z, L.hi.x), n1 = (L.hi.y, L.hi.z, R.lo.x, R.lo.y),
+//   n2 = (R.lo.z, R.hi.x, R.hi.y, R.hi.z), n3 = (left ref, right ref, -, -) as int bits
+// A child ref >= 0 names an internal node; ref < 0 names leaf ~ref.
+
+// Header block at the start of the workspace (256 bytes).
+struct WsHeader {
+    int32_t status;
+    uint32_t queue;        // persistent packet counter
+    uint32_t bounds[6];    // ordered-uint min xyz, max xyz of the means
+    float root_box[6];
+    uint32_t pad[50];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+struct Layout {
+    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, keys_alt, vals_alt, hist, total;
+    int64_t n, n_int, sort_blocks;
+};
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+inline Layout make_layout(int64_t n)
+{
+    Layout L{};
+    L.n = n;
+    L.n_int = n > 1 ? n - 1 : 0;
+    int64_t nn = n > 0 ? n : 1;
+    int64_t ni = L.n_int > 0 ? L.n_int : 1;
+    L.sort_blocks = (nn + kSortTile - 1) / kSortTile;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align256(off + bytes);
+        return o;
+    };
+    L.header = take(sizeof(WsHeader));
+    L.records = take(size_t(nn) * 64);
+    L.nodes = take(size_t(ni) * 64);
+    L.gidx = take(size_t(nn) * 4);
+    L.inv = take(size_t(nn) * 4);
+    L.codes = take(size_t(nn) * 4);
+    L.leaf_boxes = take(size_t(nn) * 24);
+    L.parent = take(size_t(2 * nn) * 4);
+    L.visit = take(size_t(ni) * 4);
+    L.keys_alt = take(size_t(nn) * 4);
+    L.vals_alt = take(size_t(nn) * 4);
+    L.hist = take(size_t(256) * L.sort_blocks * 4);
+    L.total = off;
+    return L;
+}
+
+// Descriptor stored in rs_bvh.opaque.
+struct BvhDesc {
+    uint64_t magic;
+    int64_t n;
+    float Q;
+    int32_t root;       // root ref (0: internal node 0; ~0: single leaf; unused when n == 0)
+    char *ws;
+    uint64_t ws_bytes;
+    uint64_t pad[10];
+};
+static_assert(sizeof(BvhDesc) <= sizeof(rs_bvh), "descriptor size");
+
+// ---------------------------------------------------------------- helpers
+
+__device__ inline uint32_t float_to_ordered(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__device__ inline float ordered_to_float(uint32_t u)
+{
+    uint32_t b = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    return __uint_as_float(b);
+}
+
+// 64-bit hit key: ordered bits of t1 above the Gaussian index, so that an
+// unsigned compare orders hits by (t1, index).
+__device__ inline uint64_t make_key(float t1, uint32_t gid)
+{
+    return (uint64_t(float_to_ordered(t1)) << 32) | gid;
+}
+
+__device__ inline float key_t(uint64_t k) { return ordered_to_float(uint32_t(k >> 32)); }
+
+constexpr uint64_t kKeyNone = ~0ull;
+
+}  // namespace rs

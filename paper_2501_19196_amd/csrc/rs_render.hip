@@ -1,0 +1,707 @@
+// Ray-packet traversal, ellipsoid intersection, depth-ordered compositing and
+// its adjoint, for gfx950 (wave64).
+//
+// One wavefront traces one packet of 64 rays (an 8x8 pixel tile). The whole
+// wave walks the BVH together: node and Gaussian records are fetched once per
+// wave (uniform addresses, scalar loads) and every lane tests them against its
+// own ray; a child is entered when any lane's ray overlaps it (ballot). The
+// traversal stack is wave-uniform and lives in one VGPR (entry k in lane k).
+//
+// Each lane keeps its K nearest not-yet-composited hits, ordered by the key
+// (t1, Gaussian index), in registers. A round traverses the BVH collecting
+// the K smallest keys above the previous round's last key (nodes are culled
+// against [last t, K-th t]), then composites them front to back (Eq. 3) with
+// the K_max and eps1 stops (Sec. 3, "Color Aggregation"). Rounds repeat
+// until every lane has stopped or run out of hits.
+//
+// The adjoint kernel replays the same rounds bit for bit (same code, same
+// operation order) and forms dL/dalpha front to back from the final colour,
+// the quantity the recursion of App. A.4/A.5 carries; the gradients of alpha
+// with respect to the Gaussian parameters follow App. A.6 in a cancellation
+// free form (see grad_hit). Per-Gaussian gradient contributions of a wave are
+// summed across lanes before one set of float32 atomics per Gaussian.
+#include <math.h>
+
+#include "rs_internal.h"
+
+#pragma clang fp contract(on)
+
+namespace rs {
+
+struct ViewEntry {
+    int64_t ray_offset;
+    int64_t first_packet;
+    int32_t width, height, tiles_x, pad;
+};
+
+struct RenderParams {
+    int64_t n_rays;
+    int64_t n_packets;
+    int64_t n_gauss;
+    int32_t root;
+    int32_t stack_depth;
+    float Q, eps1, t_min;
+    int32_t max_hits;
+    float bg[3];
+    uint32_t flags;
+    int32_t persistent;
+    int32_t brute;
+    int32_t zero_colour;
+    int32_t n_views;
+    int64_t packets_per_xcd;
+    ViewEntry views[RS_MAX_VIEWS];
+};
+
+constexpr float kInf = __builtin_huge_valf();
+
+// --------------------------------------------------------------- packets
+
+// Packet index -> ray index of this lane (8x8 tiles within each view).
+__device__ inline int64_t packet_ray(const RenderParams &P, int64_t pkt, int lane, bool &valid)
+{
+    if (P.n_views == 0) {
+        int64_t r = pkt * kWave + lane;
+        valid = r < P.n_rays;
+        return r;
+    }
+    int v = 0;
+    for (int k = 1; k < P.n_views; ++k)
+        if (pkt >= P.views[k].first_packet) v = k;
+    const ViewEntry &V = P.views[v];
+    int64_t local = pkt - V.first_packet;
+    int64_t ty = local / V.tiles_x, tx = local - ty * V.tiles_x;
+    int64_t x = tx * kTile + (lane & (kTile - 1));
+    int64_t y = ty * kTile + (lane / kTile);
+    valid = x < V.width && y < V.height;
+    return V.ray_offset + y * V.width + x;
+}
+
+// Consecutive tiles share Gaussians; keep runs of them on one XCD (blocks are
+// dispatched round-robin over the 8 XCDs).
+__device__ inline int64_t xcd_packet(const RenderParams &P, int64_t b)
+{
+    return (b & 7) * P.packets_per_xcd + (b >> 3);
+}
+
+// ------------------------------------------------------------ intersection
+
+struct Ray {
+    float ox, oy, oz, dx, dy, dz;
+};
+
+// Ray / confidence-ellipsoid test (Sec. 3, Prop. 1, Prop. 2) for the record
+// r0..r3 (R^T, 1/s, mean, opacity). With x = o - m, the whitened ray is
+// o' = D R^T x, d' = D R^T d (D = diag(1/s)); its squared distance to the
+// origin is h^2 = |o' x d'|^2 / |d'|^2 and o' x d' = cof(D) R^T (x cross d)
+// with cof(D) = (D1 D2, D0 D2, D0 D1): every term is a sum of squares, so flat
+// Gaussians (one scale -> 0) lose no precision to cancellation. The nearer
+// root is t1 = -b/a - sqrt((Q - h^2)/a) for b = <o',d'> >= 0 and the Viete
+// form (|o'|^2 - Q) / (a t*) otherwise (Prop. 1, App. A.1).
+__device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                     float Q, float &t1, float &h2)
+{
+    const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
+    const float wx = xy * ray.dz - xz * ray.dy;
+    const float wy = xz * ray.dx - xx * ray.dz;
+    const float wz = xx * ray.dy - xy * ray.dx;
+    // rows of R^T
+    const float a00 = r0.x, a01 = r0.y, a02 = r0.z, a10 = r0.w, a11 = r1.x, a12 = r1.y, a20 = r1.z, a21 = r1.w,
+                a22 = r2.x;
+    const float D0 = r2.y, D1 = r2.z, D2 = r2.w;
+    const float y0 = a00 * xx + a01 * xy + a02 * xz;
+    const float y1 = a10 * xx + a11 * xy + a12 * xz;
+    const float y2 = a20 * xx + a21 * xy + a22 * xz;
+    const float e0 = a00 * ray.dx + a01 * ray.dy + a02 * ray.dz;
+    const float e1 = a10 * ray.dx + a11 * ray.dy + a12 * ray.dz;
+    const float e2 = a20 * ray.dx + a21 * ray.dy + a22 * ray.dz;
+    const float v0 = a00 * wx + a01 * wy + a02 * wz;
+    const float v1 = a10 * wx + a11 * wy + a12 * wz;
+    const float v2 = a20 * wx + a21 * wy + a22 * wz;
+    const float o0 = D0 * y0, o1 = D1 * y1, o2 = D2 * y2;
+    const float d0 = D0 * e0, d1 = D1 * e1, d2 = D2 * e2;
+    const float u0 = (D1 * D2) * v0, u1 = (D0 * D2) * v1, u2 = (D0 * D1) * v2;
+    const float a = d0 * d0 + d1 * d1 + d2 * d2;
+    const float b = o0 * d0 + o1 * d1 + o2 * d2;
+    const float uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const float ia = __builtin_amdgcn_rcpf(a);
+    h2 = uu * ia;
+    if (!(h2 <= Q)) return false;
+    const float sq = __builtin_sqrtf((Q - h2) * ia);
+    const float tc = -b * ia;
+    if (b >= 0.0f) {
+        t1 = tc - sq;
+    } else {
+        const float oo = o0 * o0 + o1 * o1 + o2 * o2;
+        t1 = ((oo - Q) * ia) * __builtin_amdgcn_rcpf(tc + sq);
+    }
+    if (t1 == 0.0f) t1 = 0.0f;  // -0 -> +0 so the key order matches float order
+    return true;
+}
+
+// ------------------------------------------------------------- hit buffer
+
+template <int K>
+struct HitBuf {
+    uint64_t key[K];
+    float alpha[K];
+
+    __device__ inline void clear()
+    {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            key[s] = kKeyNone;
+            alpha[s] = 0.0f;
+        }
+    }
+
+    // entry s (s uniform) without dynamic register indexing
+    __device__ inline void get(int s, uint64_t &k, float &a) const
+    {
+        k = key[0];
+        a = alpha[0];
+#pragma unroll
+        for (int t = 1; t < K; ++t) {
+            k = (t == s) ? key[t] : k;
+            a = (t == s) ? alpha[t] : a;
+        }
+    }
+
+    // sorted insert of (k, a); the last entry falls off
+    __device__ inline void insert(uint64_t k, float a)
+    {
+#pragma unroll
+        for (int s = 0; s < K; ++s) {
+            const bool sw = k < key[s];
+            const uint64_t tk = key[s];
+            const float ta = alpha[s];
+            key[s] = sw ? k : tk;
+            alpha[s] = sw ? a : ta;
+            k = sw ? tk : k;
+            a = sw ? ta : a;
+        }
+    }
+};
+
+// ------------------------------------------------------------- compositing
+
+// One front-to-back step (Eq. 3): shared by the forward and adjoint kernels so
+// both see bit-identical T and C sequences.
+struct Accum {
+    float T, Cr, Cg, Cb;
+    int n;
+};
+
+__device__ inline void composite_step(Accum &A, float a, float cr, float cg, float cb)
+{
+    const float w = A.T * a;
+    A.Cr = __builtin_fmaf(w, cr, A.Cr);
+    A.Cg = __builtin_fmaf(w, cg, A.Cg);
+    A.Cb = __builtin_fmaf(w, cb, A.Cb);
+    const float om = 1.0f - a;
+    A.T = A.T * om;
+    A.n += 1;
+}
+
+__device__ inline bool stop_after(const Accum &A, const RenderParams &P)
+{
+    return A.T < P.eps1 || (P.max_hits > 0 && A.n >= P.max_hits);
+}
+
+// --------------------------------------------------------------- adjoint
+
+// Gradient of h^2 (and so of alpha = opacity exp(-h^2/2)) for one hit.
+// With p = o' - (b/a) d' (whitened closest point, obtained without
+// cancellation as p = (d' x (o' x d')) / a) and q_w = x - (b/a) d:
+//   dh2/dm = -2 R D p,  dh2/ds_k = -2 D_k p_k^2,  dh2/dR = 2 q_w (D p)^T,
+// and dh2/dq follows from R(q) = P(q)/|q|^2, P the homogeneous quadratic
+// form, as (<dh2/dR, dP/dq_j> - 2 q_j <dh2/dR, R>) / |q|^2. These are the
+// App. A.6 expressions regrouped: dh2/dtheta = 2<p, do'> - 2(b/a)<p, dd'>.
+struct GradOut {
+    float v[14];  // mean 3, scale 3, quat 4, opacity 1, rgb 3
+};
+
+__device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                const float *__restrict__ quat, uint32_t gid, float dLda, float alpha, GradOut &G)
+{
+    const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
+    const float wx = xy * ray.dz - xz * ray.dy;
+    const float wy = xz * ray.dx - xx * ray.dz;
+    const float wz = xx * ray.dy - xy * ray.dx;
+    const float a00 = r0.x, a01 = r0.y, a02 = r0.z, a10 = r0.w, a11 = r1.x, a12 = r1.y, a20 = r1.z, a21 = r1.w,
+                a22 = r2.x;
+    const float D0 = r2.y, D1 = r2.z, D2 = r2.w;
+    const float y0 = a00 * xx + a01 * xy + a02 * xz;
+    const float y1 = a10 * xx + a11 * xy + a12 * xz;
+    const float y2 = a20 * xx + a21 * xy + a22 * xz;
+    const float e0 = a00 * ray.dx + a01 * ray.dy + a02 * ray.dz;
+    const float e1 = a10 * ray.dx + a11 * ray.dy + a12 * ray.dz;
+    const float e2 = a20 * ray.dx + a21 * ray.dy + a22 * ray.dz;
+    const float v0 = a00 * wx + a01 * wy + a02 * wz;
+    const float v1 = a10 * wx + a11 * wy + a12 * wz;
+    const float v2 = a20 * wx + a21 * wy + a22 * wz;
+    const float o0 = D0 * y0, o1 = D1 * y1, o2 = D2 * y2;
+    const float d0 = D0 * e0, d1 = D1 * e1, d2 = D2 * e2;
+    const float u0 = (D1 * D2) * v0, u1 = (D0 * D2) * v1, u2 = (D0 * D1) * v2;
+    const float a = d0 * d0 + d1 * d1 + d2 * d2;
+    const float b = o0 * d0 + o1 * d1 + o2 * d2;
+    const float ia = 1.0f / a;
+    const float h2 = (u0 * u0 + u1 * u1 + u2 * u2) * ia;
+    // p = (d' x u) / a
+    const float p0 = (d1 * u2 - d2 * u1) * ia;
+    const float p1 = (d2 * u0 - d0 * u2) * ia;
+    const float p2 = (d0 * u1 - d1 * u0) * ia;
+    const float ba = b * ia;
+    const float qx = xx - ba * ray.dx, qy = xy - ba * ray.dy, qz = xz - ba * ray.dz;
+    const float Dp0 = D0 * p0, Dp1 = D1 * p1, Dp2 = D2 * p2;
+    const float gh = dLda * (-0.5f * alpha);  // dL/dh2
+    // z = R Dp; R_ik = RT_ki
+    const float z0 = a00 * Dp0 + a10 * Dp1 + a20 * Dp2;
+    const float z1 = a01 * Dp0 + a11 * Dp1 + a21 * Dp2;
+    const float z2 = a02 * Dp0 + a12 * Dp1 + a22 * Dp2;
+    G.v[0] = gh * (-2.0f * z0);
+    G.v[1] = gh * (-2.0f * z1);
+    G.v[2] = gh * (-2.0f * z2);
+    G.v[3] = gh * (-2.0f * Dp0 * p0);
+    G.v[4] = gh * (-2.0f * Dp1 * p1);
+    G.v[5] = gh * (-2.0f * Dp2 * p2);
+    // quaternion
+    const float4 q = reinterpret_cast<const float4 *>(quat)[gid];
+    const float qa = q.x, qb = q.y, qc = q.z, qd = q.w;
+    const float nq = qa * qa + qb * qb + qc * qc + qd * qd;
+    // <G_R, M> = 2 q_w^T M Dp for G_R = 2 q_w Dp^T
+    const float qRz = qx * z0 + qy * z1 + qz * z2;  // q_w^T R Dp
+    // dP/da = 2[[a,-d,c],[d,a,-b],[-c,b,a]] etc.; M Dp for each
+    const float ma0 = qa * Dp0 - qd * Dp1 + qc * Dp2, ma1 = qd * Dp0 + qa * Dp1 - qb * Dp2,
+                ma2 = -qc * Dp0 + qb * Dp1 + qa * Dp2;
+    const float mb0 = qb * Dp0 + qc * Dp1 + qd * Dp2, mb1 = qc * Dp0 - qb * Dp1 - qa * Dp2,
+                mb2 = qd * Dp0 + qa * Dp1 - qb * Dp2;
+    const float mc0 = -qc * Dp0 + qb * Dp1 + qa * Dp2, mc1 = qb * Dp0 + qc * Dp1 + qd * Dp2,
+                mc2 = -qa * Dp0 + qd * Dp1 - qc * Dp2;
+    const float md0 = -qd * Dp0 - qa * Dp1 + qb * Dp2, md1 = qa * Dp0 - qd * Dp1 + qc * Dp2,
+                md2 = qb * Dp0 + qc * Dp1 + qd * Dp2;
+    const float sa = 2.0f * (qx * ma0 + qy * ma1 + qz * ma2);
+    const float sb = 2.0f * (qx * mb0 + qy * mb1 + qz * mb2);
+    const float scq = 2.0f * (qx * mc0 + qy * mc1 + qz * mc2);
+    const float sd = 2.0f * (qx * md0 + qy * md1 + qz * md2);
+    const float inq = 1.0f / nq;
+    // dh2/dq_j = 2 (q_w^T dP_j Dp - 2 q_j q_w^T R Dp) / |q|^2
+    G.v[6] = gh * 2.0f * (sa - 2.0f * qa * qRz) * inq;
+    G.v[7] = gh * 2.0f * (sb - 2.0f * qb * qRz) * inq;
+    G.v[8] = gh * 2.0f * (scq - 2.0f * qc * qRz) * inq;
+    G.v[9] = gh * 2.0f * (sd - 2.0f * qd * qRz) * inq;
+    // opacity: alpha = opacity * exp(-h2/2)
+    G.v[10] = dLda * __expf(-0.5f * h2);
+}
+
+__device__ inline float wave_sum(float v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ----------------------------------------------------------------- kernel
+
+struct Ptrs {
+    const float *quat, *rgb, *origin, *dir, *tmax, *bgray, *grad;
+    float *out_rgb;
+    float4 *state;
+    float *d_mean, *d_scale, *d_quat, *d_opacity, *d_rgb;
+    int32_t *status;
+    uint32_t *queue;
+};
+
+template <int K, bool BWD, bool BRUTE>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : (K <= 24 ? 3 : 2)))) void k_render(const float4 *__restrict__ records, const float4 *__restrict__ nodes,
+                                               const int32_t *__restrict__ gidx, const int32_t *__restrict__ inv,
+                                               const Ptrs ptr, const RenderParams P)
+{
+    const int lane = threadIdx.x;
+    const uint64_t lane_bit = 1ull << lane;
+    int64_t iter_pkt = 0;
+    for (;;) {
+        int64_t pkt;
+        if (P.persistent) {
+            uint32_t p = 0;
+            if (lane == 0) p = atomicAdd(ptr.queue, 1u);
+            pkt = __builtin_amdgcn_readfirstlane(p);
+        } else {
+            if (iter_pkt > 0) break;
+            pkt = xcd_packet(P, blockIdx.x);
+        }
+        ++iter_pkt;
+        if (pkt >= P.n_packets) break;
+
+        bool valid;
+        const int64_t ray_id = packet_ray(P, pkt, lane, valid);
+        Ray ray;
+        float tmax = kInf, bgr = P.bg[0], bgg = P.bg[1], bgb = P.bg[2];
+        if (valid) {
+            ray.ox = ptr.origin[3 * ray_id];
+            ray.oy = ptr.origin[3 * ray_id + 1];
+            ray.oz = ptr.origin[3 * ray_id + 2];
+            ray.dx = ptr.dir[3 * ray_id];
+            ray.dy = ptr.dir[3 * ray_id + 1];
+            ray.dz = ptr.dir[3 * ray_id + 2];
+            if (ptr.tmax) tmax = ptr.tmax[ray_id];
+            if (ptr.bgray) {
+                bgr = ptr.bgray[3 * ray_id];
+                bgg = ptr.bgray[3 * ray_id + 1];
+                bgb = ptr.bgray[3 * ray_id + 2];
+            }
+        } else {
+            ray.ox = ray.oy = ray.oz = 0.0f;
+            ray.dx = ray.dy = 0.0f;
+            ray.dz = 1.0f;
+        }
+        // slab-test reciprocals (zero components replaced by a tiny value)
+        const float sx = fabsf(ray.dx) > 1e-20f ? ray.dx : copysignf(1e-20f, ray.dx);
+        const float sy = fabsf(ray.dy) > 1e-20f ? ray.dy : copysignf(1e-20f, ray.dy);
+        const float sz = fabsf(ray.dz) > 1e-20f ? ray.dz : copysignf(1e-20f, ray.dz);
+        const float idx = 1.0f / sx, idy = 1.0f / sy, idz = 1.0f / sz;
+
+        Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
+        bool live = valid && P.n_gauss > 0;
+        uint64_t last = 0;  // keys of this round must exceed it
+        float gr = 0.0f, gg = 0.0f, gb = 0.0f, Cor = 0.0f, Cog = 0.0f, Cob = 0.0f;
+        if (BWD && valid) {
+            gr = ptr.grad[3 * ray_id];
+            gg = ptr.grad[3 * ray_id + 1];
+            gb = ptr.grad[3 * ray_id + 2];
+            const float4 s = ptr.state[ray_id];
+            Cor = s.x;
+            Cog = s.y;
+            Cob = s.z;
+            if (gr == 0.0f && gg == 0.0f && gb == 0.0f) live = false;
+        }
+        bool overflow = false;
+
+        while (__ballot(live)) {
+            HitBuf<K> hb;
+            hb.clear();
+            const float t_lo = last == 0 ? P.t_min : fmaxf(P.t_min, key_t(last));
+            float t_hi = tmax;
+
+            auto leaf = [&](int64_t j) {
+                const int64_t js = __builtin_amdgcn_readfirstlane(int32_t(j));
+                const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
+                             r3 = records[4 * js + 3];
+                const uint32_t gid = uint32_t(gidx[js]);
+                float t1 = 0.0f, h2 = 0.0f;
+                bool cand = false;
+                uint64_t k = kKeyNone;
+                if (live && ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2)) {
+                    k = make_key(t1, gid);
+                    cand = t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
+                }
+                if (__ballot(cand)) {
+                    // every lane runs the insertion network; lanes without a candidate insert
+                    // the empty key, which moves nothing
+                    const float al = r3.w * __expf(-0.5f * h2);
+                    hb.insert(cand ? k : kKeyNone, al);
+                    if (hb.key[K - 1] != kKeyNone) t_hi = fminf(tmax, key_t(hb.key[K - 1]));
+                }
+            };
+
+            if (BRUTE) {
+                for (int64_t j = 0; j < P.n_gauss; ++j) leaf(j);
+            } else {
+                // While-while traversal: descend internal nodes until a leaf is reached (or the
+                // stack runs dry), then test that leaf; the hit buffer changes only in the leaf step.
+                constexpr int32_t kDone = INT32_MIN;
+                int32_t node = P.root;
+                int32_t sp = 0;
+                int32_t stackv = 0;
+                for (;;) {
+                    while (node >= 0) {
+                        const int64_t ns = __builtin_amdgcn_readfirstlane(node);
+                        const float4 n0 = nodes[4 * ns], n1 = nodes[4 * ns + 1], n2 = nodes[4 * ns + 2],
+                                     n3 = nodes[4 * ns + 3];
+                        // slab tests of both children against [t_lo, t_hi]
+                        const float lx0 = (n0.x - ray.ox) * idx, lx1 = (n0.w - ray.ox) * idx;
+                        const float ly0 = (n0.y - ray.oy) * idy, ly1 = (n1.x - ray.oy) * idy;
+                        const float lz0 = (n0.z - ray.oz) * idz, lz1 = (n1.y - ray.oz) * idz;
+                        const float rx0 = (n1.z - ray.ox) * idx, rx1 = (n2.y - ray.ox) * idx;
+                        const float ry0 = (n1.w - ray.oy) * idy, ry1 = (n2.z - ray.oy) * idy;
+                        const float rz0 = (n2.x - ray.oz) * idz, rz1 = (n2.w - ray.oz) * idz;
+                        float ln = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fminf(lz0, lz1));
+                        float lf = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fmaxf(lz0, lz1));
+                        float rn = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fminf(rz0, rz1));
+                        float rf = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1));
+                        // widen by a relative 2^-20 against rounding of the slab arithmetic
+                        ln -= fabsf(ln) * 9.5367431640625e-7f;
+                        rn -= fabsf(rn) * 9.5367431640625e-7f;
+                        lf += fabsf(lf) * 9.5367431640625e-7f;
+                        rf += fabsf(rf) * 9.5367431640625e-7f;
+                        const bool hl = live && ln <= lf && lf >= t_lo && ln <= t_hi;
+                        const bool hr = live && rn <= rf && rf >= t_lo && rn <= t_hi;
+                        const uint64_t bl = __ballot(hl), br = __ballot(hr);
+                        const int32_t left = __float_as_int(n3.x), right = __float_as_int(n3.y);
+                        if (bl && br) {
+                            const uint64_t pref = __ballot(hl && (!hr || ln <= rn));
+                            const bool lfirst = 2 * __popcll(pref) >= __popcll(bl | br);
+                            if (sp >= P.stack_depth) {
+                                overflow = true;
+                                node = kDone;
+                                break;
+                            }
+                            stackv = (lane == sp) ? (lfirst ? right : left) : stackv;  // lane sp holds entry sp
+                            ++sp;
+                            node = lfirst ? left : right;
+                        } else if (bl) {
+                            node = left;
+                        } else if (br) {
+                            node = right;
+                        } else if (sp == 0) {
+                            node = kDone;
+                        } else {
+                            --sp;
+                            node = __builtin_amdgcn_readlane(stackv, sp);
+                        }
+                    }
+                    if (node == kDone) break;
+                    leaf(~node);
+                    if (sp == 0) break;
+                    --sp;
+                    node = __builtin_amdgcn_readlane(stackv, sp);
+                }
+            }
+            if (overflow) {
+                if (lane == 0) atomicOr(ptr.status, kStatusStack);
+                live = false;
+                break;
+            }
+
+            // composite this round's hits front to back
+            // (the forward loop is unrolled; the adjoint's body is large, so it loops and
+            // picks slot s with a select chain instead of dynamic register indexing)
+            bool more = true;
+            constexpr int kUnroll = BWD ? 1 : K;
+#pragma unroll kUnroll
+            for (int s = 0; s < K; ++s) {
+                uint64_t key_s;
+                float al;
+                hb.get(s, key_s, al);
+                const bool act = more && live && key_s != kKeyNone;
+                more = __ballot(act) != 0;
+                if (!more) break;
+                const uint32_t gid = uint32_t(key_s & 0xffffffffu);
+                float cr = 0.0f, cg = 0.0f, cb = 0.0f;
+                if (act && !P.zero_colour) {
+                    cr = ptr.rgb[3 * gid];
+                    cg = ptr.rgb[3 * gid + 1];
+                    cb = ptr.rgb[3 * gid + 2];
+                }
+                float Tk = A.T;
+                if (act) {
+                    composite_step(A, al, cr, cg, cb);
+                }
+                const bool stopped = act && stop_after(A, P);
+                if (BWD) {
+                    GradOut G;
+#pragma unroll
+                    for (int v = 0; v < 14; ++v) G.v[v] = 0.0f;
+                    if (act) {
+                        // dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the remaining
+                        // colour of the last composited hit is T_final bg, so there dC/dalpha = T_k (c_k - bg)
+                        float dLda;
+                        if (stopped) {
+                            dLda = Tk * (gr * (cr - bgr) + gg * (cg - bgg) + gb * (cb - bgb));
+                        } else {
+                            const float rem = gr * (Cor - A.Cr) + gg * (Cog - A.Cg) + gb * (Cob - A.Cb);
+                            dLda = Tk * (gr * cr + gg * cg + gb * cb) - rem / (1.0f - al);
+                        }
+                        const int32_t js = inv[gid];
+                        const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
+                                     r3 = records[4 * js + 3];
+                        grad_hit(ray, r0, r1, r2, r3, ptr.quat, gid, dLda, al, G);
+                        const float wgt = al * Tk;
+                        G.v[11] = P.zero_colour ? 0.0f : gr * wgt;
+                        G.v[12] = P.zero_colour ? 0.0f : gg * wgt;
+                        G.v[13] = P.zero_colour ? 0.0f : gb * wgt;
+                    }
+                    // wave aggregation: lanes holding the same Gaussian are summed first
+                    uint64_t todo = __ballot(act);
+                    while (todo) {
+                        const int leader = __builtin_ctzll(todo);
+                        const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
+                        const uint64_t same = __ballot(act && gid == lg);
+                        todo &= ~same;
+                        float tot[14];
+                        if (__popcll(same) == 1) {
+#pragma unroll
+                            for (int v = 0; v < 14; ++v) tot[v] = G.v[v];
+                        } else {
+                            const bool mine = (same & lane_bit) != 0;
+#pragma unroll
+                            for (int v = 0; v < 14; ++v) tot[v] = wave_sum(mine ? G.v[v] : 0.0f);
+                        }
+                        if (lane == leader) {
+                            if (ptr.d_mean)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_mean + 3 * lg + c, tot[c]);
+                            if (ptr.d_scale)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_scale + 3 * lg + c, tot[3 + c]);
+                            if (ptr.d_quat)
+#pragma unroll
+                                for (int c = 0; c < 4; ++c) unsafeAtomicAdd(ptr.d_quat + 4 * lg + c, tot[6 + c]);
+                            if (ptr.d_opacity) unsafeAtomicAdd(ptr.d_opacity + lg, tot[10]);
+                            if (ptr.d_rgb && !P.zero_colour)
+#pragma unroll
+                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_rgb + 3 * lg + c, tot[11 + c]);
+                        }
+                    }
+                }
+                if (stopped) live = false;
+            }
+            // a lane whose buffer did not fill has consumed all its hits
+            if (live && hb.key[K - 1] == kKeyNone) live = false;
+            last = hb.key[K - 1];
+        }
+
+        if (!BWD && valid) {
+            ptr.out_rgb[3 * ray_id] = __builtin_fmaf(A.T, bgr, A.Cr);
+            ptr.out_rgb[3 * ray_id + 1] = __builtin_fmaf(A.T, bgg, A.Cg);
+            ptr.out_rgb[3 * ray_id + 2] = __builtin_fmaf(A.T, bgb, A.Cb);
+            if (ptr.state) ptr.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
+                                                           __builtin_fmaf(A.T, bgg, A.Cg),
+                                                           __builtin_fmaf(A.T, bgb, A.Cb), A.T);
+        }
+    }
+}
+
+// ------------------------------------------------------------------- host
+
+__global__ void k_zero_f32(float *p, int64_t n)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    int64_t stride = int64_t(gridDim.x) * blockDim.x;
+    for (; i < n; i += stride) p[i] = 0.0f;
+}
+
+__global__ void k_zero_queue(uint32_t *q)
+{
+    if (threadIdx.x == 0) *q = 0u;
+}
+
+static void zero(float *p, int64_t n, hipStream_t st)
+{
+    if (!p || n <= 0) return;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    k_zero_f32<<<int(blocks), 256, 0, st>>>(p, n);
+}
+
+template <int K>
+static void launch_k(bool bwd, int grid, const float4 *records, const float4 *nodes, const int32_t *gidx,
+                     const int32_t *inv, const Ptrs &ptr, const RenderParams &P, hipStream_t st)
+{
+    if (P.brute) {
+        if (bwd)
+            k_render<K, true, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+        else
+            k_render<K, false, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+    } else {
+        if (bwd)
+            k_render<K, true, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+        else
+            k_render<K, false, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+    }
+}
+
+int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                  float *out_rgb, void *state, const float *grad, const rs_grads *grads, hipStream_t st)
+{
+    const bool bwd = grad != nullptr;
+    Layout L = make_layout(D.n);
+    char *ws = D.ws;
+    WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
+
+    RenderParams P{};
+    P.n_rays = rays->n;
+    P.n_gauss = D.n;
+    P.root = D.root;
+    P.stack_depth = p->stack_depth > 0 ? p->stack_depth : 64;
+    P.Q = p->Q;
+    P.eps1 = p->eps1;
+    P.t_min = p->t_min;
+    P.max_hits = p->max_hits;
+    for (int k = 0; k < 3; ++k) P.bg[k] = p->bg[k];
+    P.flags = p->flags;
+    P.persistent = (p->flags & RS_PERSISTENT) ? 1 : 0;
+    P.brute = (p->flags & RS_BRUTE_FORCE) ? 1 : 0;
+    P.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
+    P.n_views = rays->n_views;
+    int64_t packets = 0;
+    if (rays->n_views == 0) {
+        packets = (rays->n + kWave - 1) / kWave;
+    } else {
+        for (int v = 0; v < rays->n_views; ++v) {
+            const rs_view &V = rays->views[v];
+            ViewEntry &E = P.views[v];
+            E.ray_offset = V.ray_offset;
+            E.width = V.width;
+            E.height = V.height;
+            E.tiles_x = (V.width + kTile - 1) / kTile;
+            E.first_packet = packets;
+            packets += int64_t(E.tiles_x) * ((V.height + kTile - 1) / kTile);
+        }
+    }
+    P.n_packets = packets;
+    P.packets_per_xcd = (packets + 7) / 8;
+
+    Ptrs ptr{};
+    ptr.quat = g->quat;
+    ptr.rgb = g->rgb;
+    ptr.origin = rays->origin;
+    ptr.dir = rays->dir;
+    ptr.tmax = rays->t_max;
+    ptr.bgray = rays->bg;
+    ptr.grad = grad;
+    ptr.out_rgb = out_rgb;
+    ptr.state = reinterpret_cast<float4 *>(state);
+    if (bwd && grads) {
+        ptr.d_mean = grads->d_mean;
+        ptr.d_scale = grads->d_scale;
+        ptr.d_quat = grads->d_quat;
+        ptr.d_opacity = grads->d_opacity;
+        ptr.d_rgb = grads->d_rgb;
+        zero(ptr.d_mean, 3 * g->n, st);
+        zero(ptr.d_scale, 3 * g->n, st);
+        zero(ptr.d_quat, 4 * g->n, st);
+        zero(ptr.d_opacity, g->n, st);
+        zero(ptr.d_rgb, 3 * g->n, st);
+    }
+    ptr.status = &h->status;
+    ptr.queue = &h->queue;
+
+    if (packets == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+
+    int grid;
+    if (P.persistent) {
+        k_zero_queue<<<1, 64, 0, st>>>(&h->queue);
+        int dev = 0, cus = 256;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
+        grid = int(waves < packets ? waves : packets);
+    } else {
+        grid = int(8 * P.packets_per_xcd);
+    }
+    const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
+    const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
+    const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
+    const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
+    const int K = p->kbuf > 0 ? p->kbuf : 16;
+    switch (K) {
+    case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+    case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+    case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+    case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+    default: return RS_ERR_INVALID_ARG;
+    }
+    return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+}  // namespace rs

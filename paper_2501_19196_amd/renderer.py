@@ -1,0 +1,206 @@
+"""Torch-facing wrappers of the C ABI: device memory and streams come from
+torch, every computation runs in librs.so. Also the autograd Function.
+
+Names follow the paper: Q (ellipsoid quantile, Sec. 3), eps1 (transmittance
+threshold) and max_hits (K_max, the per-ray hit cap, Sec. 3 "Color
+Aggregation").
+"""
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+@dataclass
+class Params:
+    Q: float = 11.3449
+    eps1: float = 1e-4
+    t_min: float = 0.0
+    max_hits: int = 512
+    bg: tuple = (0.0, 0.0, 0.0)
+    flags: int = 0
+    kbuf: int = 0
+    stack_depth: int = 0
+
+    def c(self):
+        p = L.rs_params()
+        p.Q, p.eps1, p.t_min, p.max_hits = float(self.Q), float(self.eps1), float(self.t_min), int(self.max_hits)
+        for k in range(3):
+            p.bg[k] = float(self.bg[k])
+        p.flags = int(self.flags)
+        p.kbuf = int(self.kbuf)
+        p.stack_depth = int(self.stack_depth)
+        p.packet_rays = 0
+        return p
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, name, dtype=torch.float32):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Gaussians:
+    mean: torch.Tensor
+    scale: torch.Tensor
+    quat: torch.Tensor
+    opacity: torch.Tensor
+    rgb: torch.Tensor
+
+    def c(self):
+        n = self.mean.shape[0]
+        for name in ("mean", "scale", "quat", "opacity", "rgb"):
+            _dev(getattr(self, name), name)
+        if self.mean.shape != (n, 3) or self.scale.shape != (n, 3) or self.quat.shape != (n, 4) or \
+                self.opacity.shape != (n,) or self.rgb.shape != (n, 3):
+            raise ValueError("gaussian arrays must be mean[n,3], scale[n,3], quat[n,4], opacity[n], rgb[n,3]")
+        return L.rs_gaussians(n, _ptr(self.mean), _ptr(self.scale), _ptr(self.quat), _ptr(self.opacity),
+                              _ptr(self.rgb))
+
+    @property
+    def n(self):
+        return int(self.mean.shape[0])
+
+
+@dataclass
+class Rays:
+    origin: torch.Tensor
+    direction: torch.Tensor
+    t_max: torch.Tensor = None
+    bg: torch.Tensor = None
+    views: list = field(default_factory=list)  # [(ray_offset, width, height)]
+
+    def c(self):
+        n = self.origin.shape[0]
+        _dev(self.origin, "origin")
+        _dev(self.direction, "direction")
+        if self.origin.shape != (n, 3) or self.direction.shape != (n, 3):
+            raise ValueError("rays must be origin[n,3], direction[n,3]")
+        if self.t_max is not None:
+            _dev(self.t_max, "t_max")
+        if self.bg is not None:
+            _dev(self.bg, "bg")
+        nv = len(self.views)
+        self._views = (L.rs_view * max(nv, 1))()
+        for i, (off, w, h) in enumerate(self.views):
+            self._views[i].ray_offset, self._views[i].width, self._views[i].height = int(off), int(w), int(h)
+        return L.rs_rays(n, _ptr(self.origin), _ptr(self.direction), _ptr(self.t_max), _ptr(self.bg), nv,
+                         C.cast(self._views, C.POINTER(L.rs_view)))
+
+    @property
+    def n(self):
+        return int(self.origin.shape[0])
+
+
+class BVH:
+    """A built BVH: the caller-owned workspace tensor plus its descriptor."""
+
+    def __init__(self, n, Q, workspace, desc):
+        self.n, self.Q, self.workspace, self.desc = n, Q, workspace, desc
+
+
+def workspace_bytes(n):
+    return int(L.lib().rs_bvh_workspace_bytes(int(n)))
+
+
+def build_bvh(g: Gaussians, params: Params, workspace=None):
+    lib = L.lib()
+    nbytes = workspace_bytes(g.n)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=g.mean.device)
+    desc = L.rs_bvh()
+    gc, pc = g.c(), params.c()
+    L.check(lib.rs_build_bvh(C.byref(gc), C.byref(pc), _ptr(workspace), C.c_size_t(workspace.numel()),
+                             C.byref(desc), _stream()), "rs_build_bvh")
+    return BVH(g.n, params.Q, workspace, desc)
+
+
+def render_fwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, out=None, state=None, want_state=True):
+    lib = L.lib()
+    n = rays.n
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
+    if want_state and state is None:
+        state = torch.empty((n, 4), dtype=torch.float32, device=rays.origin.device)
+    gc, rc, pc = g.c(), rays.c(), params.c()
+    L.check(lib.rs_render_fwd(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(out), _ptr(state),
+                              _stream()), "rs_render_fwd")
+    return out, state
+
+
+def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, state, grads=None):
+    lib = L.lib()
+    grad_rgb = _dev(grad_rgb.contiguous(), "grad_rgb")
+    if grads is None:
+        dev = g.mean.device
+        grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
+                 torch.empty_like(g.opacity), torch.empty_like(g.rgb))
+    gr = L.rs_grads(*[_ptr(t) for t in grads])
+    gc, rc, pc = g.c(), rays.c(), params.c()
+    L.check(lib.rs_render_bwd(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(grad_rgb),
+                              _ptr(state), C.byref(gr), _stream()), "rs_render_bwd")
+    return grads
+
+
+def read_status(bvh: BVH):
+    return int(L.lib().rs_read_status(C.byref(bvh.desc), _stream()))
+
+
+def download(bvh: BVH):
+    """Host copies of the built BVH (for tests)."""
+    n = bvh.n
+    ni = max(n - 1, 0)
+    codes = np.zeros(max(n, 1), np.uint32)
+    perm = np.zeros(max(n, 1), np.int32)
+    child = np.zeros((max(ni, 1), 2), np.int32)
+    boxes = np.zeros((max(ni, 1), 2, 6), np.float32)
+    leaf_boxes = np.zeros((max(n, 1), 6), np.float32)
+    bounds = np.zeros(6, np.float32)
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    L.check(L.lib().rs_bvh_download(C.byref(bvh.desc), p(codes), p(perm), p(child), p(boxes), p(leaf_boxes),
+                                    p(bounds), _stream()), "rs_bvh_download")
+    return dict(codes=codes[:n], perm=perm[:n], child=child[:ni], boxes=boxes[:ni], leaf_boxes=leaf_boxes[:n],
+                bounds=bounds)
+
+
+class RaySplatsRender(torch.autograd.Function):
+    """rgb = render(mean, scale, quat, opacity, rgb; rays). The BVH is rebuilt
+    in every forward (the parameters change every optimisation step); the
+    backward re-traverses the rays (no per-ray hit lists are stored)."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, opacity, rgb, origin, direction, params, views):
+        g = Gaussians(mean.contiguous(), scale.contiguous(), quat.contiguous(), opacity.contiguous(),
+                      rgb.contiguous())
+        rays = Rays(origin.contiguous(), direction.contiguous(), views=list(views or []))
+        bvh = build_bvh(g, params)
+        out, state = render_fwd(bvh, g, rays, params)
+        ctx.saved = (bvh, g, rays, params, state)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        bvh, g, rays, params, state = ctx.saved
+        dm, ds, dq, do, dc = render_bwd(bvh, g, rays, params, grad_out.contiguous(), state)
+        return dm, ds, dq, do, dc, None, None, None, None
+
+
+def render(mean, scale, quat, opacity, rgb, origin, direction, params=None, views=None):
+    return RaySplatsRender.apply(mean, scale, quat, opacity, rgb, origin, direction, params or Params(), views)

