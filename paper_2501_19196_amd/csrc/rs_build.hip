@@ -322,35 +322,61 @@ __device__ inline float ld_agent(const float *p)
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Bottom-up union of child boxes: one thread per leaf climbs while it is the
-// second child to arrive at a node (atomic visit counter).
+// Bottom-up box of every internal node: one thread per leaf climbs while it
+// is the second child to arrive at a node (atomic visit counter), computing
+// that node's box from its two children (leaf boxes or boxes of internal
+// nodes finished earlier). No box is carried across iterations: each node's
+// own box goes to ibox[node] and k_fill_nodes copies the child boxes into
+// the traversal nodes afterwards.
+__device__ inline void child_box(int32_t ref, const float *__restrict__ leaf_boxes, const float *ibox, float *b)
+{
+    const float *src = ref < 0 ? leaf_boxes + 6 * int64_t(~ref) : ibox + 6 * int64_t(ref);
+    if (ref < 0) {
+        for (int k = 0; k < 6; ++k) b[k] = src[k];
+    } else {
+        for (int k = 0; k < 6; ++k) b[k] = ld_agent(src + k);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_refit(const float *__restrict__ leaf_boxes, const int32_t *__restrict__ parent,
-                                               float *nodes_f, uint32_t *visit, int64_t n, WsHeader *h)
+                                               const float4 *__restrict__ nodes, float *ibox, uint32_t *visit,
+                                               int64_t n)
 {
     int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= n) return;
-    float b[6];
-    for (int k = 0; k < 6; ++k) b[k] = leaf_boxes[6 * j + k];
-    int32_t ref = ~int32_t(j);
     int32_t node = parent[j];
     while (node >= 0) {
-        float *nf = nodes_f + 16 * int64_t(node);
-        int32_t left = __float_as_int(nf[12]);
-        int slot = (left == ref) ? 0 : 1;
-        // L box at floats [0, 6), R box at [6, 12)
-        for (int k = 0; k < 6; ++k) nf[6 * slot + k] = b[k];
         __threadfence();
-        uint32_t old = atomicAdd(&visit[node], 1u);
+        const uint32_t old = atomicAdd(&visit[node], 1u);
         if (old == 0) return;
         __threadfence();
+        const float4 n3 = nodes[4 * int64_t(node) + 3];
+        float bl[6], br[6];
+        child_box(__float_as_int(n3.x), leaf_boxes, ibox, bl);
+        child_box(__float_as_int(n3.y), leaf_boxes, ibox, br);
+        float *dst = ibox + 6 * int64_t(node);
         for (int k = 0; k < 3; ++k) {
-            b[k] = fminf(ld_agent(nf + k), ld_agent(nf + 6 + k));
-            b[3 + k] = fmaxf(ld_agent(nf + 3 + k), ld_agent(nf + 9 + k));
+            dst[k] = fminf(bl[k], br[k]);
+            dst[3 + k] = fmaxf(bl[3 + k], br[3 + k]);
         }
-        ref = node;
         node = parent[n + node];
     }
-    for (int k = 0; k < 6; ++k) h->root_box[k] = b[k];
+}
+
+// Child boxes into the traversal nodes (floats [0, 6) left, [6, 12) right).
+__global__ __launch_bounds__(256) void k_fill_nodes(const float *__restrict__ leaf_boxes, const float *__restrict__ ibox,
+                                                    float *__restrict__ nodes_f, int64_t n_int, WsHeader *h)
+{
+    int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_int) return;
+    float *nf = nodes_f + 16 * i;
+    for (int c = 0; c < 2; ++c) {
+        const int32_t ref = __float_as_int(nf[12 + c]);
+        const float *src = ref < 0 ? leaf_boxes + 6 * int64_t(~ref) : ibox + 6 * int64_t(ref);
+        for (int k = 0; k < 6; ++k) nf[6 * c + k] = src[k];
+    }
+    if (i == 0)
+        for (int k = 0; k < 6; ++k) h->root_box[k] = ibox[k];
 }
 
 // ------------------------------------------------------------------- host
@@ -396,7 +422,10 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
         k_fill_u32<<<blocks_for(L.n_int, 256) < 2048 ? blocks_for(L.n_int, 256) : 2048, 256, 0, st>>>(visit, L.n_int,
                                                                                                        0u);
         k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(codes, n, nodes, parent);
-        k_refit<<<bgrid, 256, 0, st>>>(leaf_boxes, parent, reinterpret_cast<float *>(nodes), visit, n, h);
+        float *ibox = reinterpret_cast<float *>(ws + L.ibox);
+        k_refit<<<bgrid, 256, 0, st>>>(leaf_boxes, parent, nodes, ibox, visit, n);
+        k_fill_nodes<<<blocks_for(L.n_int, 256), 256, 0, st>>>(leaf_boxes, ibox, reinterpret_cast<float *>(nodes),
+                                                                L.n_int, h);
     } else {
         (void)hipMemcpyAsync(h->root_box, leaf_boxes, 6 * sizeof(float), hipMemcpyDeviceToDevice, st);
     }

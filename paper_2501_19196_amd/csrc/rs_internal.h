@@ -40,7 +40,7 @@ struct WsHeader {
 static_assert(sizeof(WsHeader) == 256, "header size");
 
 struct Layout {
-    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, keys_alt, vals_alt, hist, total;
+    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, ibox, keys_alt, vals_alt, hist, total;
     int64_t n, n_int, sort_blocks;
 };
 
@@ -69,6 +69,7 @@ inline Layout make_layout(int64_t n)
     L.leaf_boxes = take(size_t(nn) * 24);
     L.parent = take(size_t(2 * nn) * 4);
     L.visit = take(size_t(ni) * 4);
+    L.ibox = take(size_t(ni) * 24);
     L.keys_alt = take(size_t(nn) * 4);
     L.vals_alt = take(size_t(nn) * 4);
     L.hist = take(size_t(256) * L.sort_blocks * 4);
