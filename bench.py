@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--kbuf", type=int, default=0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=96)
+    ap.add_argument("--cpu-rays", type=int, default=3000)
     ap.add_argument("--parity-rays", type=int, default=256)
     return ap.parse_args()
 
