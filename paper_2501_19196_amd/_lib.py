@@ -8,7 +8,7 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "librs.so")
+LIB_PATH = os.environ.get("RS_LIBRARY", os.path.join(_HERE, "librs.so"))
 
 RS_OK = 0
 RS_ERR_INVALID_ARG = -1
@@ -22,11 +22,12 @@ RS_ERR_UNSUPPORTED = -7
 RS_BRUTE_FORCE = 1 << 0
 RS_PERSISTENT = 1 << 1
 RS_ZERO_COLOUR = 1 << 2
+RS_COUNTERS = 1 << 3
 RS_MAX_VIEWS = 64
 
 # Every symbol include/raysplats.h declares.
 EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", "rs_build_bvh", "rs_render_fwd",
-           "rs_render_bwd", "rs_read_status", "rs_status_string", "rs_bvh_download")
+           "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download")
 
 
 class rs_gaussians(C.Structure):
@@ -91,6 +92,8 @@ def lib():
     L.rs_render_bwd.restype = C.c_int
     L.rs_read_status.argtypes = [C.POINTER(rs_bvh), P]
     L.rs_read_status.restype = C.c_int
+    L.rs_read_counters.argtypes = [C.POINTER(rs_bvh), P, P]
+    L.rs_read_counters.restype = C.c_int
     L.rs_status_string.argtypes = [C.c_int]
     L.rs_status_string.restype = C.c_char_p
     L.rs_bvh_download.argtypes = [C.POINTER(rs_bvh), P, P, P, P, P, P, P]

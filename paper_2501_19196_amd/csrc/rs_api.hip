@@ -29,7 +29,7 @@ static int check_params(const rs_params *p)
     if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32) return RS_ERR_INVALID_ARG;
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
     if (p->packet_rays != 0 && p->packet_rays != 64) return RS_ERR_INVALID_ARG;
-    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR)) return RS_ERR_INVALID_ARG;
+    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS)) return RS_ERR_INVALID_ARG;
     return RS_OK;
 }
 
@@ -144,6 +144,20 @@ int rs_read_status(const rs_bvh *bvh, void *stream)
     if (hipMemcpy(&s, D.ws + L.header, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     if (s & kStatusStack) return RS_ERR_STACK_OVERFLOW;
     if (s & kStatusNonfinite) return RS_ERR_NONFINITE;
+    return RS_OK;
+}
+
+int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream)
+{
+    if (!bvh || !out) return RS_ERR_INVALID_ARG;
+    BvhDesc D;
+    memcpy(&D, bvh, sizeof(D));
+    if (D.magic != kMagic || !D.ws) return RS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RS_ERR_HIP;
+    WsHeader h;
+    Layout L = make_layout(D.n);
+    if (hipMemcpy(&h, D.ws + L.header, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+    for (int k = 0; k < 8; ++k) out[k] = h.counters[k];
     return RS_OK;
 }
 

@@ -35,7 +35,8 @@ struct WsHeader {
     uint32_t queue;        // persistent packet counter
     uint32_t bounds[6];    // ordered-uint min xyz, max xyz of the means
     float root_box[6];
-    uint32_t pad[50];
+    uint64_t counters[8];  // instrumentation (RS_COUNTERS)
+    uint32_t pad[34];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 

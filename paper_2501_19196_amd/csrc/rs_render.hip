@@ -47,8 +47,8 @@ struct RenderParams {
     int32_t persistent;
     int32_t brute;
     int32_t zero_colour;
+    int32_t count;
     int32_t n_views;
-    int64_t packets_per_xcd;
     ViewEntry views[RS_MAX_VIEWS];
 };
 
@@ -74,13 +74,6 @@ __device__ inline int64_t packet_ray(const RenderParams &P, int64_t pkt, int lan
     int64_t y = ty * kTile + (lane / kTile);
     valid = x < V.width && y < V.height;
     return V.ray_offset + y * V.width + x;
-}
-
-// Consecutive tiles share Gaussians; keep runs of them on one XCD (blocks are
-// dispatched round-robin over the 8 XCDs).
-__device__ inline int64_t xcd_packet(const RenderParams &P, int64_t b)
-{
-    return (b & 7) * P.packets_per_xcd + (b >> 3);
 }
 
 // ------------------------------------------------------------ intersection
@@ -142,42 +135,31 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
 
 template <int K>
 struct HitBuf {
-    uint64_t key[K];
-    float alpha[K];
+    uint64_t key[K];  // sorted ascending; kKeyNone marks an empty slot
 
     __device__ inline void clear()
     {
 #pragma unroll
-        for (int s = 0; s < K; ++s) {
-            key[s] = kKeyNone;
-            alpha[s] = 0.0f;
-        }
+        for (int s = 0; s < K; ++s) key[s] = kKeyNone;
     }
 
-    // entry s (s uniform) without dynamic register indexing
-    __device__ inline void get(int s, uint64_t &k, float &a) const
+    // drop the front entry (static register moves: no dynamic indexing)
+    __device__ inline void pop_front()
     {
-        k = key[0];
-        a = alpha[0];
 #pragma unroll
-        for (int t = 1; t < K; ++t) {
-            k = (t == s) ? key[t] : k;
-            a = (t == s) ? alpha[t] : a;
-        }
+        for (int s = 0; s + 1 < K; ++s) key[s] = key[s + 1];
+        key[K - 1] = kKeyNone;
     }
 
-    // sorted insert of (k, a); the last entry falls off
-    __device__ inline void insert(uint64_t k, float a)
+    // sorted insert of k; the last entry falls off (inserting kKeyNone changes nothing)
+    __device__ inline void insert(uint64_t k)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
             const bool sw = k < key[s];
             const uint64_t tk = key[s];
-            const float ta = alpha[s];
             key[s] = sw ? k : tk;
-            alpha[s] = sw ? a : ta;
             k = sw ? tk : k;
-            a = sw ? ta : a;
         }
     }
 };
@@ -309,16 +291,44 @@ struct Ptrs {
     float *d_mean, *d_scale, *d_quat, *d_opacity, *d_rgb;
     int32_t *status;
     uint32_t *queue;
+    unsigned long long *counters;
 };
 
+// Slab-test constants: a box [lo, hi] is entered at max_k (near_k - o_k) / d_k and
+// left at min_k (far_k - o_k) / d_k, evaluated as fma(plane, 1/d, -o/d). The far
+// distance and the round's upper bound are widened by a relative 2^-19 plus the
+// rounding scale of o/d, so rounding never culls a box the exact test keeps.
+constexpr float kWiden = 1.9073486328125e-6f;  // 2^-19
+
+struct Slab {
+    float ix, iy, iz, nx, ny, nz, pad;
+};
+
+__device__ inline float widen(float t, float pad) { return __builtin_fmaf(fabsf(t), kWiden, t) + pad; }
+
+// Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
+// (512 / waves): the adjoint carries the gradient temporaries as well.
+#ifndef RS_FWD16_WAVES
+#define RS_FWD16_WAVES 5
+#endif
+#ifndef RS_BWD16_WAVES
+#define RS_BWD16_WAVES 4
+#endif
+constexpr int waves_for(int K, bool bwd)
+{
+    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? 3 : 2))) : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? 4 : 3)));
+}
+
 template <int K, bool BWD, bool BRUTE>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 : (K <= 24 ? 3 : 2)))) void k_render(const float4 *__restrict__ records, const float4 *__restrict__ nodes,
-                                               const int32_t *__restrict__ gidx, const int32_t *__restrict__ inv,
-                                               const Ptrs ptr, const RenderParams P)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K, BWD)))) void k_render(
+    const float4 *__restrict__ records, const float4 *__restrict__ nodes, const int32_t *__restrict__ gidx,
+    const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
 {
     const int lane = threadIdx.x;
     const uint64_t lane_bit = 1ull << lane;
     int64_t iter_pkt = 0;
+    // work counters (wave-uniform, kept in scalar registers; written when P.count)
+    uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0;
     for (;;) {
         int64_t pkt;
         if (P.persistent) {
@@ -327,10 +337,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
             pkt = __builtin_amdgcn_readfirstlane(p);
         } else {
             if (iter_pkt > 0) break;
-            pkt = xcd_packet(P, blockIdx.x);
+            pkt = blockIdx.x;
         }
         ++iter_pkt;
         if (pkt >= P.n_packets) break;
+        ++c_pkt;
 
         bool valid;
         const int64_t ray_id = packet_ray(P, pkt, lane, valid);
@@ -354,11 +365,27 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
             ray.dx = ray.dy = 0.0f;
             ray.dz = 1.0f;
         }
-        // slab-test reciprocals (zero components replaced by a tiny value)
-        const float sx = fabsf(ray.dx) > 1e-20f ? ray.dx : copysignf(1e-20f, ray.dx);
-        const float sy = fabsf(ray.dy) > 1e-20f ? ray.dy : copysignf(1e-20f, ray.dy);
-        const float sz = fabsf(ray.dz) > 1e-20f ? ray.dz : copysignf(1e-20f, ray.dz);
-        const float idx = 1.0f / sx, idy = 1.0f / sy, idz = 1.0f / sz;
+        // slab constants (zero direction components replaced by a tiny value of the same sign)
+        Slab sl;
+        {
+            const float sx = fabsf(ray.dx) > 1e-20f ? ray.dx : copysignf(1e-20f, ray.dx);
+            const float sy = fabsf(ray.dy) > 1e-20f ? ray.dy : copysignf(1e-20f, ray.dy);
+            const float sz = fabsf(ray.dz) > 1e-20f ? ray.dz : copysignf(1e-20f, ray.dz);
+            sl.ix = 1.0f / sx;
+            sl.iy = 1.0f / sy;
+            sl.iz = 1.0f / sz;
+            sl.nx = -ray.ox * sl.ix;
+            sl.ny = -ray.oy * sl.iy;
+            sl.nz = -ray.oz * sl.iz;
+            sl.pad = kWiden * fmaxf(fmaxf(fabsf(sl.nx), fabsf(sl.ny)), fabsf(sl.nz));
+        }
+        // when every valid lane's direction has the same sign per axis, the near and far
+        // planes of a box are chosen once per wave (scalar selects)
+        const uint64_t vmask = __ballot(valid);
+        const uint64_t bx = __ballot(valid && sl.ix >= 0.0f), by = __ballot(valid && sl.iy >= 0.0f),
+                       bz = __ballot(valid && sl.iz >= 0.0f);
+        const bool uni = (bx == 0 || bx == vmask) && (by == 0 || by == vmask) && (bz == 0 || bz == vmask);
+        const bool px = bx != 0, py = by != 0, pz = bz != 0;
 
         Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
         bool live = valid && P.n_gauss > 0;
@@ -379,8 +406,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
         while (__ballot(live)) {
             HitBuf<K> hb;
             hb.clear();
+            ++c_round;
             const float t_lo = last == 0 ? P.t_min : fmaxf(P.t_min, key_t(last));
-            float t_hi = tmax;
+            float t_hi_w = widen(tmax, sl.pad);
 
             auto leaf = [&](int64_t j) {
                 const int64_t js = __builtin_amdgcn_readfirstlane(int32_t(j));
@@ -394,12 +422,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                     k = make_key(t1, gid);
                     cand = t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
                 }
-                if (__ballot(cand)) {
+                const uint64_t cmask = __ballot(cand);
+                if (P.count) {
+                    ++c_leaf;
+                    c_lleaf += __popcll(__ballot(live));
+                    c_lbuf += __popcll(cmask);
+                }
+                if (cmask) {
                     // every lane runs the insertion network; lanes without a candidate insert
                     // the empty key, which moves nothing
-                    const float al = r3.w * __expf(-0.5f * h2);
-                    hb.insert(cand ? k : kKeyNone, al);
-                    if (hb.key[K - 1] != kKeyNone) t_hi = fminf(tmax, key_t(hb.key[K - 1]));
+                    hb.insert(cand ? k : kKeyNone);
+                    if (hb.key[K - 1] != kKeyNone) t_hi_w = widen(fminf(tmax, key_t(hb.key[K - 1])), sl.pad);
                 }
             };
 
@@ -417,26 +450,41 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                         const int64_t ns = __builtin_amdgcn_readfirstlane(node);
                         const float4 n0 = nodes[4 * ns], n1 = nodes[4 * ns + 1], n2 = nodes[4 * ns + 2],
                                      n3 = nodes[4 * ns + 3];
-                        // slab tests of both children against [t_lo, t_hi]
-                        const float lx0 = (n0.x - ray.ox) * idx, lx1 = (n0.w - ray.ox) * idx;
-                        const float ly0 = (n0.y - ray.oy) * idy, ly1 = (n1.x - ray.oy) * idy;
-                        const float lz0 = (n0.z - ray.oz) * idz, lz1 = (n1.y - ray.oz) * idz;
-                        const float rx0 = (n1.z - ray.ox) * idx, rx1 = (n2.y - ray.ox) * idx;
-                        const float ry0 = (n1.w - ray.oy) * idy, ry1 = (n2.z - ray.oy) * idy;
-                        const float rz0 = (n2.x - ray.oz) * idz, rz1 = (n2.w - ray.oz) * idz;
-                        float ln = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fminf(lz0, lz1));
-                        float lf = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fmaxf(lz0, lz1));
-                        float rn = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fminf(rz0, rz1));
-                        float rf = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1));
-                        // widen by a relative 2^-20 against rounding of the slab arithmetic
-                        ln -= fabsf(ln) * 9.5367431640625e-7f;
-                        rn -= fabsf(rn) * 9.5367431640625e-7f;
-                        lf += fabsf(lf) * 9.5367431640625e-7f;
-                        rf += fabsf(rf) * 9.5367431640625e-7f;
-                        const bool hl = live && ln <= lf && lf >= t_lo && ln <= t_hi;
-                        const bool hr = live && rn <= rf && rf >= t_lo && rn <= t_hi;
+                        // child boxes: L = (n0.xyz, n0.w n1.xy), R = (n1.zw n2.x, n2.yzw)
+                        float ln, lf, rn, rf;
+                        if (uni) {
+                            ln = fmaxf(fmaxf(__builtin_fmaf(px ? n0.x : n0.w, sl.ix, sl.nx),
+                                             __builtin_fmaf(py ? n0.y : n1.x, sl.iy, sl.ny)),
+                                       __builtin_fmaf(pz ? n0.z : n1.y, sl.iz, sl.nz));
+                            lf = fminf(fminf(__builtin_fmaf(px ? n0.w : n0.x, sl.ix, sl.nx),
+                                             __builtin_fmaf(py ? n1.x : n0.y, sl.iy, sl.ny)),
+                                       __builtin_fmaf(pz ? n1.y : n0.z, sl.iz, sl.nz));
+                            rn = fmaxf(fmaxf(__builtin_fmaf(px ? n1.z : n2.y, sl.ix, sl.nx),
+                                             __builtin_fmaf(py ? n1.w : n2.z, sl.iy, sl.ny)),
+                                       __builtin_fmaf(pz ? n2.x : n2.w, sl.iz, sl.nz));
+                            rf = fminf(fminf(__builtin_fmaf(px ? n2.y : n1.z, sl.ix, sl.nx),
+                                             __builtin_fmaf(py ? n2.z : n1.w, sl.iy, sl.ny)),
+                                       __builtin_fmaf(pz ? n2.w : n2.x, sl.iz, sl.nz));
+                        } else {
+                            const float lx0 = __builtin_fmaf(n0.x, sl.ix, sl.nx), lx1 = __builtin_fmaf(n0.w, sl.ix, sl.nx);
+                            const float ly0 = __builtin_fmaf(n0.y, sl.iy, sl.ny), ly1 = __builtin_fmaf(n1.x, sl.iy, sl.ny);
+                            const float lz0 = __builtin_fmaf(n0.z, sl.iz, sl.nz), lz1 = __builtin_fmaf(n1.y, sl.iz, sl.nz);
+                            const float rx0 = __builtin_fmaf(n1.z, sl.ix, sl.nx), rx1 = __builtin_fmaf(n2.y, sl.ix, sl.nx);
+                            const float ry0 = __builtin_fmaf(n1.w, sl.iy, sl.ny), ry1 = __builtin_fmaf(n2.z, sl.iy, sl.ny);
+                            const float rz0 = __builtin_fmaf(n2.x, sl.iz, sl.nz), rz1 = __builtin_fmaf(n2.w, sl.iz, sl.nz);
+                            ln = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fminf(lz0, lz1));
+                            lf = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fmaxf(lz0, lz1));
+                            rn = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fminf(rz0, rz1));
+                            rf = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1));
+                        }
+                        const bool hl = live && fmaxf(ln, t_lo) <= fminf(widen(lf, sl.pad), t_hi_w);
+                        const bool hr = live && fmaxf(rn, t_lo) <= fminf(widen(rf, sl.pad), t_hi_w);
                         const uint64_t bl = __ballot(hl), br = __ballot(hr);
                         const int32_t left = __float_as_int(n3.x), right = __float_as_int(n3.y);
+                        if (P.count) {
+                            ++c_node;
+                            c_lchild += __popcll(bl) + __popcll(br);
+                        }
                         if (bl && br) {
                             const uint64_t pref = __ballot(hl && (!hr || ln <= rn));
                             const bool lfirst = 2 * __popcll(pref) >= __popcll(bl | br);
@@ -472,28 +520,36 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                 break;
             }
 
-            // composite this round's hits front to back
-            // (the forward loop is unrolled; the adjoint's body is large, so it loops and
-            // picks slot s with a select chain instead of dynamic register indexing)
+            // composite this round's hits front to back; alpha is recomputed from the record
+            // with the leaf test's own arithmetic. The buffer is consumed from its front.
+            const uint64_t round_last = hb.key[K - 1];
             bool more = true;
-            constexpr int kUnroll = BWD ? 1 : K;
-#pragma unroll kUnroll
             for (int s = 0; s < K; ++s) {
-                uint64_t key_s;
-                float al;
-                hb.get(s, key_s, al);
+                const uint64_t key_s = hb.key[0];
+                hb.pop_front();
                 const bool act = more && live && key_s != kKeyNone;
-                more = __ballot(act) != 0;
+                const uint64_t act_mask = __ballot(act);
+                more = act_mask != 0;
                 if (!more) break;
+                c_lcomp += __popcll(act_mask);
                 const uint32_t gid = uint32_t(key_s & 0xffffffffu);
-                float cr = 0.0f, cg = 0.0f, cb = 0.0f;
-                if (act && !P.zero_colour) {
-                    cr = ptr.rgb[3 * gid];
-                    cg = ptr.rgb[3 * gid + 1];
-                    cb = ptr.rgb[3 * gid + 2];
-                }
-                float Tk = A.T;
+                float al = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
+                float4 r0, r1, r2, r3;
+                const float Tk = A.T;
                 if (act) {
+                    const int32_t js = inv[gid];
+                    r0 = records[4 * js + 0];
+                    r1 = records[4 * js + 1];
+                    r2 = records[4 * js + 2];
+                    r3 = records[4 * js + 3];
+                    float t1, h2;
+                    ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2);
+                    al = r3.w * __expf(-0.5f * h2);
+                    if (!P.zero_colour) {
+                        cr = ptr.rgb[3 * gid];
+                        cg = ptr.rgb[3 * gid + 1];
+                        cb = ptr.rgb[3 * gid + 2];
+                    }
                     composite_step(A, al, cr, cg, cb);
                 }
                 const bool stopped = act && stop_after(A, P);
@@ -511,9 +567,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                             const float rem = gr * (Cor - A.Cr) + gg * (Cog - A.Cg) + gb * (Cob - A.Cb);
                             dLda = Tk * (gr * cr + gg * cg + gb * cb) - rem / (1.0f - al);
                         }
-                        const int32_t js = inv[gid];
-                        const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
-                                     r3 = records[4 * js + 3];
                         grad_hit(ray, r0, r1, r2, r3, ptr.quat, gid, dLda, al, G);
                         const float wgt = al * Tk;
                         G.v[11] = P.zero_colour ? 0.0f : gr * wgt;
@@ -521,7 +574,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                         G.v[13] = P.zero_colour ? 0.0f : gb * wgt;
                     }
                     // wave aggregation: lanes holding the same Gaussian are summed first
-                    uint64_t todo = __ballot(act);
+                    uint64_t todo = act_mask;
                     while (todo) {
                         const int leader = __builtin_ctzll(todo);
                         const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
@@ -556,8 +609,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                 if (stopped) live = false;
             }
             // a lane whose buffer did not fill has consumed all its hits
-            if (live && hb.key[K - 1] == kKeyNone) live = false;
-            last = hb.key[K - 1];
+            if (live && round_last == kKeyNone) live = false;
+            last = round_last;
         }
 
         if (!BWD && valid) {
@@ -568,6 +621,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(K <= 16 ? 4 
                                                            __builtin_fmaf(A.T, bgg, A.Cg),
                                                            __builtin_fmaf(A.T, bgb, A.Cb), A.T);
         }
+    }
+    if (P.count && lane == 0 && c_pkt > 0) {
+        atomicAdd(ptr.counters + 0, (unsigned long long)c_pkt);
+        atomicAdd(ptr.counters + 1, (unsigned long long)c_node);
+        atomicAdd(ptr.counters + 2, (unsigned long long)c_leaf);
+        atomicAdd(ptr.counters + 3, (unsigned long long)c_round);
+        atomicAdd(ptr.counters + 4, (unsigned long long)c_lleaf);
+        atomicAdd(ptr.counters + 5, (unsigned long long)c_lbuf);
+        atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
+        atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
     }
 }
 
@@ -632,6 +695,7 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     P.persistent = (p->flags & RS_PERSISTENT) ? 1 : 0;
     P.brute = (p->flags & RS_BRUTE_FORCE) ? 1 : 0;
     P.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
+    P.count = (p->flags & RS_COUNTERS) ? 1 : 0;
     P.n_views = rays->n_views;
     int64_t packets = 0;
     if (rays->n_views == 0) {
@@ -649,7 +713,6 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
         }
     }
     P.n_packets = packets;
-    P.packets_per_xcd = (packets + 7) / 8;
 
     Ptrs ptr{};
     ptr.quat = g->quat;
@@ -675,6 +738,7 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     }
     ptr.status = &h->status;
     ptr.queue = &h->queue;
+    ptr.counters = reinterpret_cast<unsigned long long *>(h->counters);
 
     if (packets == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 
@@ -687,13 +751,15 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
         int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
         grid = int(waves < packets ? waves : packets);
     } else {
-        grid = int(8 * P.packets_per_xcd);
+        grid = int(packets);
     }
     const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
     const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
     const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
     const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
-    const int K = p->kbuf > 0 ? p->kbuf : 16;
+    // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
+    // the default is the fastest measured size of each pass on MI355X
+    const int K = p->kbuf > 0 ? p->kbuf : (bwd ? 16 : 24);
     switch (K) {
     case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
     case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;

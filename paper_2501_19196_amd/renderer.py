@@ -163,6 +163,17 @@ def read_status(bvh: BVH):
     return int(L.lib().rs_read_status(C.byref(bvh.desc), _stream()))
 
 
+COUNTER_NAMES = ("packets", "node_visits", "leaf_visits", "rounds", "lane_leaf_tests", "lane_hits_buffered",
+                 "lane_composited", "lane_child_overlaps")
+
+
+def read_counters(bvh: BVH):
+    out = np.zeros(8, np.uint64)
+    L.check(L.lib().rs_read_counters(C.byref(bvh.desc), out.ctypes.data_as(C.c_void_p), _stream()),
+            "rs_read_counters")
+    return dict(zip(COUNTER_NAMES, (int(x) for x in out)))
+
+
 def download(bvh: BVH):
     """Host copies of the built BVH (for tests)."""
     n = bvh.n
