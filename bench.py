@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=3000)
     ap.add_argument("--parity-rays", type=int, default=256)
+    ap.add_argument("--profile", action="store_true",
+                    help="one warm-up and one step, then a 256 MiB device copy that calibrates the "
+                         "FETCH_SIZE / WRITE_SIZE counters; prints no JSON line")
     return ap.parse_args()
 
 
@@ -106,6 +109,18 @@ def main():
     def fwd_step():
         bvh = R.build_bvh(g, p, workspace=ws)
         R.render_fwd(bvh, g, rays, p, out=out, state=None)
+
+    if args.profile:
+        step(False)
+        torch.cuda.synchronize()
+        step(False)
+        torch.cuda.synchronize()
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = src.clone()  # reads and writes exactly 256 MiB
+        torch.cuda.synchronize()
+        del src, dst
+        print("[bench] profile step done", file=sys.stderr, flush=True)
+        return
 
     for _ in range(args.warmup):
         step(False)

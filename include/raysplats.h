@@ -97,8 +97,8 @@ typedef struct {
 
 /* Renderer knobs. Q: ellipsoid quantile (Sec. 3; > 0). eps1: transmittance
  * threshold (>= 0). t_min: minimum hit depth. max_hits: K_max (0 = unbounded).
- * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 24 for
- * the forward, 16 for the adjoint; the result does not depend on it).
+ * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 24; the
+ * result does not depend on it).
  * stack_depth: traversal stack entries (1..64; 0 = 64). packet_rays: rays per
  * wavefront packet (64; 0 = 64). */
 typedef struct {
@@ -169,10 +169,12 @@ int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
 int rs_read_status(const rs_bvh *bvh, void *stream);
 
 /* Synchronise `stream` and copy the work counters accumulated by render calls
- * made with RS_COUNTERS since the last rs_build_bvh (host uint64 out[8]):
+ * made with RS_COUNTERS since the last rs_build_bvh (host uint64 out[12]):
  * [0] ray packets, [1] inner-node visits, [2] leaf visits, [3] traversal
  * rounds (all per wavefront), [4] lane leaf tests on live rays, [5] hits
- * entering a lane's buffer, [6] composited hits, [7] lane child-box overlaps.
+ * entering a lane's buffer, [6] composited hits, [7] lane child-box overlaps,
+ * [8] adjoint: per-wave gradient groups (distinct Gaussians per slot),
+ * [9]-[11] reserved (0).
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 

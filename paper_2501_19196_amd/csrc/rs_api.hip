@@ -157,7 +157,7 @@ int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream)
     WsHeader h;
     Layout L = make_layout(D.n);
     if (hipMemcpy(&h, D.ws + L.header, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
-    for (int k = 0; k < 8; ++k) out[k] = h.counters[k];
+    for (int k = 0; k < 12; ++k) out[k] = h.counters[k];
     return RS_OK;
 }
 

@@ -20,7 +20,7 @@ __global__ void k_init_header(WsHeader *h)
     if (threadIdx.x == 0) {
         h->status = 0;
         h->queue = 0;
-        for (int k = 0; k < 8; ++k) h->counters[k] = 0;
+        for (int k = 0; k < 12; ++k) h->counters[k] = 0;
         for (int k = 0; k < 3; ++k) {
             h->bounds[k] = 0xffffffffu;
             h->bounds[3 + k] = 0u;
@@ -133,18 +133,22 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_hist(const uint32_t *__rest
     hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = hs[threadIdx.x];
 }
 
-// Exclusive scan of the digit-major histogram (one workgroup).
-__global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist, int64_t m)
+// Exclusive scan of the digit-major histogram in two steps: each workgroup
+// scans one digit's row over the tiles and records the row total, then one
+// workgroup scans the 256 totals into digit bases.
+__global__ __launch_bounds__(256) void k_sort_scan_rows(uint32_t *__restrict__ hist, int64_t nblocks,
+                                                        uint32_t *__restrict__ totals)
 {
-    __shared__ uint32_t s[1024];
-    int t = threadIdx.x;
-    int64_t per = (m + 1023) / 1024;
-    int64_t b = t * per, e = min(b + per, m);
+    __shared__ uint32_t s[256];
+    const int t = threadIdx.x;
+    uint32_t *row = hist + int64_t(blockIdx.x) * nblocks;
+    const int64_t per = (nblocks + 255) / 256;
+    const int64_t b = t * per, e = min(b + per, nblocks);
     uint32_t sum = 0;
-    for (int64_t i = b; i < e; ++i) sum += hist[i];
+    for (int64_t i = b; i < e; ++i) sum += row[i];
     s[t] = sum;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
+    for (int off = 1; off < 256; off <<= 1) {
         uint32_t v = t >= off ? s[t - off] : 0u;
         __syncthreads();
         s[t] += v;
@@ -152,10 +156,27 @@ __global__ __launch_bounds__(1024) void k_sort_scan(uint32_t *__restrict__ hist,
     }
     uint32_t run = s[t] - sum;
     for (int64_t i = b; i < e; ++i) {
-        uint32_t v = hist[i];
-        hist[i] = run;
+        uint32_t v = row[i];
+        row[i] = run;
         run += v;
     }
+    if (t == 255) totals[blockIdx.x] = s[255];
+}
+
+__global__ __launch_bounds__(256) void k_sort_scan_bases(uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t s[256];
+    const int t = threadIdx.x;
+    const uint32_t mine = totals[t];
+    s[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        uint32_t v = t >= off ? s[t - off] : 0u;
+        __syncthreads();
+        s[t] += v;
+        __syncthreads();
+    }
+    totals[256 + t] = s[t] - mine;  // exclusive base of digit t
 }
 
 // Stable scatter: within a tile, keys are ranked among equal digits in input
@@ -165,12 +186,12 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *__r
                                                              const uint32_t *__restrict__ vin,
                                                              uint32_t *__restrict__ kout, uint32_t *__restrict__ vout,
                                                              int64_t n, int shift, const uint32_t *__restrict__ hist,
-                                                             int64_t nblocks)
+                                                             int64_t nblocks, const uint32_t *__restrict__ bases)
 {
     __shared__ uint32_t run[256];
     __shared__ uint32_t wcount[kSortBlock / kWave][256];
     const int t = threadIdx.x, w = t / kWave, lane = t % kWave;
-    run[t] = hist[int64_t(t) * nblocks + blockIdx.x];
+    run[t] = bases[t] + hist[int64_t(t) * nblocks + blockIdx.x];
     const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     int64_t base = int64_t(blockIdx.x) * kSortTile;
     for (int c = 0; c < kSortItems; ++c) {
@@ -325,16 +346,27 @@ __device__ inline float ld_agent(const float *p)
 
 // Bottom-up box of every internal node: one thread per leaf climbs while it
 // is the second child to arrive at a node (atomic visit counter), computing
-// that node's box from its two children (leaf boxes or boxes of internal
-// nodes finished earlier). No box is carried across iterations: each node's
-// own box goes to ibox[node] and k_fill_nodes copies the child boxes into
-// the traversal nodes afterwards.
+// that node's box from its two children (leaf boxes, written by an earlier
+// kernel, or boxes of internal nodes finished by other threads). No box is
+// carried across iterations: each node's box goes to ibox[node] and
+// k_fill_nodes copies the child boxes into the traversal nodes afterwards.
+//
+// Hand-off without cache write-backs: ibox is written with agent-scope
+// (write-through) stores and read with agent-scope loads, and a thread waits
+// for its stores to complete before its next visit atomic, so a thread that
+// sees the counter at 1 finds the sibling's box at the coherence point.
+__device__ inline void st_agent(float *p, float v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 __device__ inline void child_box(int32_t ref, const float *__restrict__ leaf_boxes, const float *ibox, float *b)
 {
-    const float *src = ref < 0 ? leaf_boxes + 6 * int64_t(~ref) : ibox + 6 * int64_t(ref);
     if (ref < 0) {
+        const float *src = leaf_boxes + 6 * int64_t(~ref);
         for (int k = 0; k < 6; ++k) b[k] = src[k];
     } else {
+        const float *src = ibox + 6 * int64_t(ref);
         for (int k = 0; k < 6; ++k) b[k] = ld_agent(src + k);
     }
 }
@@ -347,19 +379,18 @@ __global__ __launch_bounds__(256) void k_refit(const float *__restrict__ leaf_bo
     if (j >= n) return;
     int32_t node = parent[j];
     while (node >= 0) {
-        __threadfence();
-        const uint32_t old = atomicAdd(&visit[node], 1u);
+        const uint32_t old = __hip_atomic_fetch_add(&visit[node], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (old == 0) return;
-        __threadfence();
         const float4 n3 = nodes[4 * int64_t(node) + 3];
         float bl[6], br[6];
         child_box(__float_as_int(n3.x), leaf_boxes, ibox, bl);
         child_box(__float_as_int(n3.y), leaf_boxes, ibox, br);
         float *dst = ibox + 6 * int64_t(node);
         for (int k = 0; k < 3; ++k) {
-            dst[k] = fminf(bl[k], br[k]);
-            dst[3 + k] = fmaxf(bl[3 + k], br[3 + k]);
+            st_agent(dst + k, fminf(bl[k], br[k]));
+            st_agent(dst + 3 + k, fmaxf(bl[3 + k], br[3 + k]));
         }
+        __builtin_amdgcn_s_waitcnt(0);  // the box is at the coherence point before the next visit atomic
         node = parent[n + node];
     }
 }
@@ -396,6 +427,7 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
     uint32_t *kalt = reinterpret_cast<uint32_t *>(ws + L.keys_alt);
     uint32_t *valt = reinterpret_cast<uint32_t *>(ws + L.vals_alt);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + L.hist);
+    uint32_t *totals = reinterpret_cast<uint32_t *>(ws + L.totals);
     float4 *records = reinterpret_cast<float4 *>(ws + L.records);
     float4 *nodes = reinterpret_cast<float4 *>(ws + L.nodes);
     float *leaf_boxes = reinterpret_cast<float *>(ws + L.leaf_boxes);
@@ -412,8 +444,9 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
     for (int pass = 0; pass < 4; ++pass) {
         int shift = 8 * pass;
         k_sort_hist<<<int(nb), kSortBlock, 0, st>>>(ka, n, shift, hist, nb);
-        k_sort_scan<<<1, 1024, 0, st>>>(hist, 256 * nb);
-        k_sort_scatter<<<int(nb), kSortBlock, 0, st>>>(ka, va, kb, vb, n, shift, hist, nb);
+        k_sort_scan_rows<<<256, 256, 0, st>>>(hist, nb, totals);
+        k_sort_scan_bases<<<1, 256, 0, st>>>(totals);
+        k_sort_scatter<<<int(nb), kSortBlock, 0, st>>>(ka, va, kb, vb, n, shift, hist, nb, totals + 256);
         uint32_t *t;
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;

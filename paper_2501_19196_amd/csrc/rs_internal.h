@@ -35,13 +35,13 @@ struct WsHeader {
     uint32_t queue;        // persistent packet counter
     uint32_t bounds[6];    // ordered-uint min xyz, max xyz of the means
     float root_box[6];
-    uint64_t counters[8];  // instrumentation (RS_COUNTERS)
-    uint32_t pad[34];
+    uint64_t counters[12];  // instrumentation (RS_COUNTERS)
+    uint32_t pad[26];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
 struct Layout {
-    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, ibox, keys_alt, vals_alt, hist, total;
+    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, ibox, keys_alt, vals_alt, hist, totals, gacc, total;
     int64_t n, n_int, sort_blocks;
 };
 
@@ -74,6 +74,8 @@ inline Layout make_layout(int64_t n)
     L.keys_alt = take(size_t(nn) * 4);
     L.vals_alt = take(size_t(nn) * 4);
     L.hist = take(size_t(256) * L.sort_blocks * 4);
+    L.totals = take(size_t(512) * 4);
+    L.gacc = take(size_t(nn) * 64);
     L.total = off;
     return L;
 }

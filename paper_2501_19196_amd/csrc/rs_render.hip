@@ -275,10 +275,31 @@ __device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1
     G.v[10] = dLda * __expf(-0.5f * h2);
 }
 
-__device__ inline float wave_sum(float v)
+// Sum 16 per-lane values over the wavefront, transposed: after the call lane l
+// holds the wave total of value l >> 2 (exchange halves at distances 32, 16, 8
+// and 4, then fold the remaining two lane bits): 17 shuffles instead of 16 x 6.
+__device__ inline float wave_sum16_transposed(const float (&in)[16], int lane)
 {
+    float v8[8], v4[4], v2[2];
+    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    for (int i = 0; i < 8; ++i) {
+        const float keep = b5 ? in[i + 8] : in[i], send = b5 ? in[i] : in[i + 8];
+        v8[i] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const float keep = b4 ? v8[i + 4] : v8[i], send = b4 ? v8[i] : v8[i + 4];
+        v4[i] = keep + __shfl_xor(send, 16);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const float keep = b3 ? v4[i + 2] : v4[i], send = b3 ? v4[i] : v4[i + 2];
+        v2[i] = keep + __shfl_xor(send, 8);
+    }
+    float v = (b2 ? v2[1] : v2[0]) + __shfl_xor(b2 ? v2[0] : v2[1], 4);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
     return v;
 }
 
@@ -292,6 +313,7 @@ struct Ptrs {
     int32_t *status;
     uint32_t *queue;
     unsigned long long *counters;
+    float *gacc;  // adjoint accumulator, 16 floats per Gaussian (see k_scatter_grads)
 };
 
 // Slab-test constants: a box [lo, hi] is entered at max_k (near_k - o_k) / d_k and
@@ -328,7 +350,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
     const uint64_t lane_bit = 1ull << lane;
     int64_t iter_pkt = 0;
     // work counters (wave-uniform, kept in scalar registers; written when P.count)
-    uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0;
+    uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
+             c_group = 0;
     for (;;) {
         int64_t pkt;
         if (P.persistent) {
@@ -573,37 +596,25 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                         G.v[12] = P.zero_colour ? 0.0f : gg * wgt;
                         G.v[13] = P.zero_colour ? 0.0f : gb * wgt;
                     }
-                    // wave aggregation: lanes holding the same Gaussian are summed first
+                    // wave aggregation: for each distinct Gaussian among the active lanes, the
+                    // lanes holding it are summed (transposed butterfly) and one 14-lane atomic
+                    // instruction adds the totals to its 64-byte accumulator line
                     uint64_t todo = act_mask;
                     while (todo) {
                         const int leader = __builtin_ctzll(todo);
                         const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
                         const uint64_t same = __ballot(act && gid == lg);
                         todo &= ~same;
-                        float tot[14];
-                        if (__popcll(same) == 1) {
+                        ++c_group;
+                        const bool mine = (same & lane_bit) != 0;
+                        float in[16];
 #pragma unroll
-                            for (int v = 0; v < 14; ++v) tot[v] = G.v[v];
-                        } else {
-                            const bool mine = (same & lane_bit) != 0;
-#pragma unroll
-                            for (int v = 0; v < 14; ++v) tot[v] = wave_sum(mine ? G.v[v] : 0.0f);
-                        }
-                        if (lane == leader) {
-                            if (ptr.d_mean)
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_mean + 3 * lg + c, tot[c]);
-                            if (ptr.d_scale)
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_scale + 3 * lg + c, tot[3 + c]);
-                            if (ptr.d_quat)
-#pragma unroll
-                                for (int c = 0; c < 4; ++c) unsafeAtomicAdd(ptr.d_quat + 4 * lg + c, tot[6 + c]);
-                            if (ptr.d_opacity) unsafeAtomicAdd(ptr.d_opacity + lg, tot[10]);
-                            if (ptr.d_rgb && !P.zero_colour)
-#pragma unroll
-                                for (int c = 0; c < 3; ++c) unsafeAtomicAdd(ptr.d_rgb + 3 * lg + c, tot[11 + c]);
-                        }
+                        for (int v = 0; v < 14; ++v) in[v] = mine ? G.v[v] : 0.0f;
+                        in[14] = 0.0f;
+                        in[15] = 0.0f;
+                        const float tot = wave_sum16_transposed(in, lane);
+                        if ((lane & 3) == 0 && (lane >> 2) < 14)
+                            unsafeAtomicAdd(ptr.gacc + 16 * int64_t(lg) + (lane >> 2), tot);
                     }
                 }
                 if (stopped) live = false;
@@ -631,6 +642,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         atomicAdd(ptr.counters + 5, (unsigned long long)c_lbuf);
         atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
         atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
+        atomicAdd(ptr.counters + 8, (unsigned long long)c_group);
     }
 }
 
@@ -641,6 +653,34 @@ __global__ void k_zero_f32(float *p, int64_t n)
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     int64_t stride = int64_t(gridDim.x) * blockDim.x;
     for (; i < n; i += stride) p[i] = 0.0f;
+}
+
+// Accumulator (16 floats per Gaussian: mean 3, scale 3, quat 4, opacity 1,
+// rgb 3, 2 unused) -> the caller's gradient arrays.
+__global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict__ gacc, int64_t n, float *d_mean,
+                                                       float *d_scale, float *d_quat, float *d_opacity, float *d_rgb,
+                                                       int zero_colour)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 a = gacc[4 * i], b = gacc[4 * i + 1], c = gacc[4 * i + 2], d = gacc[4 * i + 3];
+    if (d_mean) {
+        d_mean[3 * i] = a.x;
+        d_mean[3 * i + 1] = a.y;
+        d_mean[3 * i + 2] = a.z;
+    }
+    if (d_scale) {
+        d_scale[3 * i] = a.w;
+        d_scale[3 * i + 1] = b.x;
+        d_scale[3 * i + 2] = b.y;
+    }
+    if (d_quat) reinterpret_cast<float4 *>(d_quat)[i] = make_float4(b.z, b.w, c.x, c.y);
+    if (d_opacity) d_opacity[i] = c.z;
+    if (d_rgb) {
+        d_rgb[3 * i] = zero_colour ? 0.0f : c.w;
+        d_rgb[3 * i + 1] = zero_colour ? 0.0f : d.x;
+        d_rgb[3 * i + 2] = zero_colour ? 0.0f : d.y;
+    }
 }
 
 __global__ void k_zero_queue(uint32_t *q)
@@ -730,43 +770,45 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
         ptr.d_quat = grads->d_quat;
         ptr.d_opacity = grads->d_opacity;
         ptr.d_rgb = grads->d_rgb;
-        zero(ptr.d_mean, 3 * g->n, st);
-        zero(ptr.d_scale, 3 * g->n, st);
-        zero(ptr.d_quat, 4 * g->n, st);
-        zero(ptr.d_opacity, g->n, st);
-        zero(ptr.d_rgb, 3 * g->n, st);
+        ptr.gacc = reinterpret_cast<float *>(ws + L.gacc);
+        zero(ptr.gacc, 16 * g->n, st);
     }
     ptr.status = &h->status;
     ptr.queue = &h->queue;
     ptr.counters = reinterpret_cast<unsigned long long *>(h->counters);
 
-    if (packets == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+    if (packets > 0) {
 
-    int grid;
-    if (P.persistent) {
-        k_zero_queue<<<1, 64, 0, st>>>(&h->queue);
-        int dev = 0, cus = 256;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
-        grid = int(waves < packets ? waves : packets);
-    } else {
-        grid = int(packets);
+        int grid;
+        if (P.persistent) {
+            k_zero_queue<<<1, 64, 0, st>>>(&h->queue);
+            int dev = 0, cus = 256;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
+            grid = int(waves < packets ? waves : packets);
+        } else {
+            grid = int(packets);
+        }
+        const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
+        const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
+        const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
+        const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
+        // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
+        // the default is the fastest measured size of each pass on MI355X
+        const int K = p->kbuf > 0 ? p->kbuf : 24;
+        switch (K) {
+        case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+        case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+        case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+        case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+        default: return RS_ERR_INVALID_ARG;
+        }
     }
-    const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
-    const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
-    const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
-    const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
-    // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
-    // the default is the fastest measured size of each pass on MI355X
-    const int K = p->kbuf > 0 ? p->kbuf : (bwd ? 16 : 24);
-    switch (K) {
-    case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-    case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-    case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-    case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-    default: return RS_ERR_INVALID_ARG;
-    }
+    if (bwd && g->n > 0)
+        k_scatter_grads<<<int((g->n + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(ptr.gacc), g->n,
+                                                                  ptr.d_mean, ptr.d_scale, ptr.d_quat, ptr.d_opacity,
+                                                                  ptr.d_rgb, P.zero_colour);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 

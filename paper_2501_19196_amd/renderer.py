@@ -164,11 +164,11 @@ def read_status(bvh: BVH):
 
 
 COUNTER_NAMES = ("packets", "node_visits", "leaf_visits", "rounds", "lane_leaf_tests", "lane_hits_buffered",
-                 "lane_composited", "lane_child_overlaps")
+                 "lane_composited", "lane_child_overlaps", "grad_groups", "r9", "r10", "r11")
 
 
 def read_counters(bvh: BVH):
-    out = np.zeros(8, np.uint64)
+    out = np.zeros(12, np.uint64)
     L.check(L.lib().rs_read_counters(C.byref(bvh.desc), out.ctypes.data_as(C.c_void_p), _stream()),
             "rs_read_counters")
     return dict(zip(COUNTER_NAMES, (int(x) for x in out)))
