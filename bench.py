@@ -19,7 +19,6 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s fwd and fwd+bwd at 1M Gaussians, % HBM roofline, vs oracle error"
-HBM_PEAK_GBS = 8000.0
 
 
 def parse():
@@ -31,7 +30,7 @@ def parse():
     ap.add_argument("--kbuf", type=int, default=0)
     ap.add_argument("--persistent", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-rays", type=int, default=3000)
+    ap.add_argument("--cpu-rays", type=int, default=8000)
     ap.add_argument("--parity-rays", type=int, default=256)
     ap.add_argument("--profile", action="store_true",
                     help="one warm-up and one step, then a 256 MiB device copy that calibrates the "
@@ -158,14 +157,37 @@ def main():
     mrays_f = nr / (ms_fwd * 1e-3) / 1e6
     mrays_render = nr / (med["fwd"] * 1e-3) / 1e6
 
-    # algorithmic (compulsory) bytes of the dominant kernel: the adjoint render reads every ray
-    # (origin, dir 24 B, grad 12 B, state 16 B), every Gaussian record, index and raw parameters it
-    # needs (64 + 4 + 4 + 16 + 12 B), every BVH node (64 B) once, and writes 56 B of gradient per Gaussian
-    bwd_bytes = nr * (24 + 12 + 16) + n * (64 + 4 + 4 + 16 + 12) + (n - 1) * 64 + n * 56
-    fwd_bytes = nr * (24 + 12 + 16) + n * (64 + 4 + 12) + (n - 1) * 64
+    # Algorithmic FP32 work of the render kernels, from the library's work counters
+    # (one untimed forward + adjoint with RS_COUNTERS). Per-unit FLOPs are counted from
+    # the kernels' expressions (an FMA is 2, min/max/compare/rcp/sqrt/exp are 1):
+    #   child-box slab test whose box the lane's ray overlaps   22
+    #   ray / ellipsoid test of a live lane at a visited leaf   90
+    #   composited hit (alpha recomputed + Eq. 3 step)          110
+    #   adjoint of a composited hit (dL/dalpha + App. A.6)      265
+    pc = R.Params(kbuf=args.kbuf, flags=flags | 8)
+    bvh_c = R.build_bvh(g, pc, workspace=ws)
+    R.render_fwd(bvh_c, g, rays, pc, out=out, state=state)
+    cf = R.read_counters(bvh_c)
+    R.render_bwd(bvh_c, g, rays, pc, torch.sign(out - target) * (1.0 / (3.0 * nr)), state, grads=grads)
+    cb = {k: R.read_counters(bvh_c)[k] - cf[k] for k in cf}
+    fwd_flops = 22.0 * cf["lane_child_overlaps"] + 90.0 * cf["lane_leaf_tests"] + 110.0 * cf["lane_composited"]
+    bwd_flops = 22.0 * cb["lane_child_overlaps"] + 90.0 * cb["lane_leaf_tests"] + \
+        (110.0 + 265.0) * cb["lane_composited"]
     dom = "bwd" if med["bwd"] >= med["fwd"] else "fwd"
-    dom_bytes = bwd_bytes if dom == "bwd" else fwd_bytes
-    achieved = dom_bytes / (med[dom] * 1e-3) / 1e9
+    dom_flops = bwd_flops if dom == "bwd" else fwd_flops
+    achieved = dom_flops / (med[dom] * 1e-3) / 1e12
+
+    # HBM traffic per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used
+    # only when they were taken on the current kernel source
+    traffic = None
+    try:
+        import hashlib
+        rec = json.load(open(os.path.join(ROOT, "profiles", "render_traffic.json")))
+        src = open(os.path.join(ROOT, "paper_2501_19196_amd", "csrc", "rs_render.hip"), "rb").read()
+        if rec.get("rs_render_sha256") == hashlib.sha256(src).hexdigest() and rec.get("workload") == w["name"]:
+            traffic = rec[f"render_{dom}_bytes"]
+    except (OSError, KeyError, ValueError):
+        traffic = None
 
     # parity on a seeded sample of pixels against the FP64 oracle
     err = None
@@ -211,14 +233,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
-                   "kbuf": p.kbuf or 16, "persistent": bool(args.persistent), "step": "bvh+fwd+L1+bwd"},
+                   "kbuf": p.kbuf or 24, "persistent": bool(args.persistent), "step": "bvh+fwd+L1+bwd"},
         "fwd_mrays_s": round(mrays_f, 3),
         "render_only_fwd_mrays_s": round(mrays_render, 3),
         "ms_fwd_step": round(ms_fwd, 4),
         "kernel_ms_median": {k: round(v, 4) for k, v in med.items()},
-        "roofline": {"bound": "hbm", "kernel": f"render_{dom}", "achieved": round(achieved, 2),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5),
-                     "traffic": None, "algorithmic_bytes": int(dom_bytes)},
+        "roofline": {"bound": "alu", "kernel": f"render_{dom}", "achieved": round(achieved, 3), "peak": 157.3,
+                     "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": traffic,
+                     "algorithmic_flops": float(dom_flops)},
+        "work_per_ray": {k: round(v / nr, 2) for k, v in cf.items() if v},
         "device_status": status,
         "parity": err,
         "cpu_baseline": cpu,
