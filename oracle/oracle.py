@@ -73,7 +73,7 @@ def lib():
         L.orc_morton_codes.argtypes = [C.c_int64, P, P, P, P]
         L.orc_sort_codes.argtypes = [C.c_int64, P, P, P]
         L.orc_radix_tree.argtypes = [C.c_int64, P, P, P]
-        L.orc_mesh_closest.argtypes = [C.c_int64, P, P, C.c_int64, P, P, C.c_double, P, P]
+        L.orc_mesh_closest.argtypes = [C.c_int64, P, P, C.c_int64, P, P, C.c_double, P, P, C.c_double, P]
         _lib = L
     return _lib
 
@@ -279,13 +279,17 @@ def radix_tree(sorted_codes):
     return child[:m], leaf[:m].astype(bool)
 
 
-def mesh_closest(verts, tris, origin, direction, t_eps=1e-9):
-    """Brute-force FP64 closest triangle hit per ray: (t[n] (inf = miss), tri[n] (-1 = miss))."""
+def mesh_closest(verts, tris, origin, direction, t_eps=1e-9, edge=0.0, want_amb=False):
+    """Brute-force FP64 closest triangle hit per ray: (t[n] (inf = miss), tri[n] (-1 = miss)[, amb[n]])."""
     v = np.ascontiguousarray(verts, np.float32)
     t = np.ascontiguousarray(tris, np.int32)
     o = np.ascontiguousarray(origin, np.float64).reshape(-1, 3)
     d = np.ascontiguousarray(direction, np.float64).reshape(-1, 3)
     n = o.shape[0]
     th = np.zeros(n); tri = np.zeros(n, np.int64)
-    lib().orc_mesh_closest(t.shape[0], _ptr(v), _ptr(t), n, _ptr(o), _ptr(d), float(t_eps), _ptr(th), _ptr(tri))
+    amb = np.zeros(n, np.int32)
+    lib().orc_mesh_closest(t.shape[0], _ptr(v), _ptr(t), n, _ptr(o), _ptr(d), float(t_eps), _ptr(th), _ptr(tri),
+                           float(edge), _ptr(amb))
+    if want_amb:
+        return th, tri, amb.astype(bool)
     return th, tri
