@@ -178,6 +178,72 @@ int rs_read_status(const rs_bvh *bvh, void *stream);
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 
+/* ------------------------------------------------------ mesh + Gaussians */
+/* The paper combines triangle meshes with Gaussians for mirror reflections
+ * and shadows (Sec. 1, Figs. 1 and 3-6) without giving a shading model. This
+ * library implements the following one:
+ *   primary ray: closest triangle hit t_m (Moller-Trumbore, both faces,
+ *     t > 0); Gaussians with t1 < t_m composite to (C_p, T_p); without a
+ *     triangle hit the pixel is C_p + T_p * bg.
+ *   at a hit P with unit normal n facing the ray and unit light direction l:
+ *     mirror triangles weigh a reflection by mirror_reflectance and a diffuse
+ *     term by mirror_diffuse; other triangles are diffuse (weight 1).
+ *   reflection ray from P + offset*n along d - 2 (d.n) n: Gaussians up to
+ *     its own closest triangle hit; background bg if it hits none, black if it
+ *     does (one bounce): C_r.
+ *   shadow ray from P + offset*n to the light: 0 if a triangle blocks it,
+ *     else the transmittance T_s of the Gaussians on the segment.
+ *   pixel = C_p + T_p (w_m C_r + w_d * albedo * max(0, n.l) * intensity * T_s).
+ * The K_max / eps1 rules apply to every ray. Gradients flow through the
+ * Gaussian hits of all three rays. */
+typedef struct {
+    int64_t n_verts, n_tris;
+    const float *verts;      /* device [n_verts][3] */
+    const int32_t *tris;     /* device [n_tris][3] vertex indices (out-of-range indices
+                                set RS_ERR_NONFINITE and read vertex 0) */
+    const int32_t *material; /* device [n_tris]: 1 mirror, 0 diffuse; NULL = all diffuse */
+} rs_mesh;
+
+typedef struct {
+    float light[3];           /* point light position */
+    float intensity, albedo;  /* light intensity, grey diffuse albedo */
+    float mirror_reflectance; /* reflection weight of mirror triangles */
+    float mirror_diffuse;     /* diffuse weight of mirror triangles */
+    float offset;             /* secondary-ray origin offset along the normal */
+} rs_shading;
+
+/* light (2,-2,5), intensity 1, albedo 0.8, mirror weights 0.8 / 0.2, offset 1e-4 */
+void rs_default_shading(rs_shading *s);
+
+/* Build a triangle BVH (same LBVH builder over triangle centroids) in a
+ * caller workspace of rs_bvh_workspace_bytes(m->n_tris) bytes. */
+int rs_build_mesh_bvh(const rs_mesh *m, void *ws, size_t ws_bytes, rs_bvh *out, void *stream);
+
+/* Closest (any_hit = 0) or any (any_hit = 1) triangle hit per ray with
+ * 0 < t < t_limit[k] (t_limit NULL = +inf; rays with t_limit <= 0 are
+ * skipped). Writes t_hit[k] (+inf when none) and tri[k] (-1 when none),
+ * device arrays of rays->n entries. */
+int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
+                  int32_t *tri, void *stream);
+
+/* Per-frame device scratch of the mesh render for n rays (secondary rays,
+ * their states and the terms the adjoint needs), 256-byte aligned. */
+size_t rs_mesh_frame_bytes(int64_t n_rays);
+
+/* Forward render of Gaussians + mesh with reflection and shadow rays. The
+ * reflection and shadow rays of all pixels are traced together in one
+ * persistent launch (two ray sets, one packet queue). `frame` must be kept
+ * for rs_render_mesh_bwd. */
+int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
+                       const rs_shading *sh, const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame,
+                       void *stream);
+
+/* Adjoint of rs_render_mesh_fwd with respect to the Gaussian parameters
+ * (the mesh and the light carry no gradient). Overwrites `out`. */
+int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
+                       const rs_shading *sh, const rs_rays *rays, const rs_params *p, const float *grad_rgb,
+                       void *frame, rs_grads *out, void *stream);
+
 /* Human-readable text of a status code (static string). */
 const char *rs_status_string(int code);
 

@@ -27,7 +27,9 @@ RS_MAX_VIEWS = 64
 
 # Every symbol include/raysplats.h declares.
 EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", "rs_build_bvh", "rs_render_fwd",
-           "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download")
+           "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download",
+           "rs_default_shading", "rs_build_mesh_bvh", "rs_trace_mesh", "rs_mesh_frame_bytes", "rs_render_mesh_fwd",
+           "rs_render_mesh_bwd")
 
 
 class rs_gaussians(C.Structure):
@@ -57,6 +59,16 @@ class rs_grads(C.Structure):
 
 class rs_bvh(C.Structure):
     _fields_ = [("opaque", C.c_uint64 * 16)]
+
+
+class rs_mesh(C.Structure):
+    _fields_ = [("n_verts", C.c_int64), ("n_tris", C.c_int64), ("verts", C.c_void_p), ("tris", C.c_void_p),
+                ("material", C.c_void_p)]
+
+
+class rs_shading(C.Structure):
+    _fields_ = [("light", C.c_float * 3), ("intensity", C.c_float), ("albedo", C.c_float),
+                ("mirror_reflectance", C.c_float), ("mirror_diffuse", C.c_float), ("offset", C.c_float)]
 
 
 class RaySplatsError(RuntimeError):
@@ -98,6 +110,21 @@ def lib():
     L.rs_status_string.restype = C.c_char_p
     L.rs_bvh_download.argtypes = [C.POINTER(rs_bvh), P, P, P, P, P, P, P]
     L.rs_bvh_download.restype = C.c_int
+    L.rs_default_shading.argtypes = [C.POINTER(rs_shading)]
+    L.rs_default_shading.restype = None
+    L.rs_build_mesh_bvh.argtypes = [C.POINTER(rs_mesh), P, C.c_size_t, C.POINTER(rs_bvh), P]
+    L.rs_build_mesh_bvh.restype = C.c_int
+    L.rs_trace_mesh.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_rays), P, C.c_int, P, P, P]
+    L.rs_trace_mesh.restype = C.c_int
+    L.rs_mesh_frame_bytes.argtypes = [C.c_int64]
+    L.rs_mesh_frame_bytes.restype = C.c_size_t
+    L.rs_render_mesh_fwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_mesh),
+                                     C.POINTER(rs_shading), C.POINTER(rs_rays), C.POINTER(rs_params), P, P, P]
+    L.rs_render_mesh_fwd.restype = C.c_int
+    L.rs_render_mesh_bwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_mesh),
+                                     C.POINTER(rs_shading), C.POINTER(rs_rays), C.POINTER(rs_params), P, P,
+                                     C.POINTER(rs_grads), P]
+    L.rs_render_mesh_bwd.restype = C.c_int
     _lib = L
     return L
 

@@ -4,12 +4,6 @@
 
 #include "rs_internal.h"
 
-namespace rs {
-int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st);
-int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
-                  void *state, const float *grad, const rs_grads *grads, hipStream_t st);
-}  // namespace rs
-
 using namespace rs;
 
 static bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -56,7 +50,7 @@ static int check_bvh(const rs_bvh *b, const rs_gaussians *g, const rs_params *p,
 {
     if (!b) return RS_ERR_INVALID_ARG;
     memcpy(&D, b, sizeof(D));
-    if (D.magic != kMagic || !D.ws) return RS_ERR_INVALID_ARG;
+    if (D.magic != kMagic || !D.ws || D.kind != kKindGaussians) return RS_ERR_INVALID_ARG;
     if (D.n != g->n || D.Q != p->Q) return RS_ERR_BVH_MISMATCH;
     return RS_OK;
 }
@@ -97,6 +91,7 @@ int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_
     D.root = g->n >= 2 ? 0 : ~0;
     D.ws = static_cast<char *>(ws);
     D.ws_bytes = ws_bytes;
+    D.kind = kKindGaussians;
     memset(out, 0, sizeof(*out));
     memcpy(out, &D, sizeof(D));
     return RS_OK;
@@ -129,6 +124,117 @@ int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
     if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, 16))) return RS_ERR_INVALID_ARG;
     return launch_render(D, g, rays, p, nullptr, const_cast<void *>(ray_state), grad_rgb, out,
                          static_cast<hipStream_t>(stream));
+}
+
+static int check_mesh(const rs_mesh *m)
+{
+    if (!m || m->n_tris < 0 || m->n_tris > 0x7ffffffeLL || m->n_verts < 0) return RS_ERR_INVALID_ARG;
+    if (m->n_tris > 0 && (!m->verts || !m->tris || m->n_verts == 0)) return RS_ERR_INVALID_ARG;
+    return RS_OK;
+}
+
+static int check_mesh_bvh(const rs_bvh *b, const rs_mesh *m, BvhDesc &D)
+{
+    if (!b) return RS_ERR_INVALID_ARG;
+    memcpy(&D, b, sizeof(D));
+    if (D.magic != kMagic || !D.ws || D.kind != kKindMesh) return RS_ERR_INVALID_ARG;
+    if (m && D.n != m->n_tris) return RS_ERR_BVH_MISMATCH;
+    return RS_OK;
+}
+
+static int check_shading(const rs_shading *sh)
+{
+    if (!sh) return RS_ERR_INVALID_ARG;
+    const float v[9] = {sh->light[0], sh->light[1], sh->light[2], sh->intensity, sh->albedo, sh->mirror_reflectance,
+                        sh->mirror_diffuse, sh->offset, 0.0f};
+    for (float x : v)
+        if (!(x == x) || x == __builtin_huge_valf() || x == -__builtin_huge_valf()) return RS_ERR_INVALID_ARG;
+    if (sh->offset < 0.0f || sh->mirror_reflectance < 0.0f || sh->mirror_diffuse < 0.0f) return RS_ERR_INVALID_ARG;
+    return RS_OK;
+}
+
+void rs_default_shading(rs_shading *s)
+{
+    if (!s) return;
+    s->light[0] = 2.0f;
+    s->light[1] = -2.0f;
+    s->light[2] = 5.0f;
+    s->intensity = 1.0f;
+    s->albedo = 0.8f;
+    s->mirror_reflectance = 0.8f;
+    s->mirror_diffuse = 0.2f;
+    s->offset = 1e-4f;
+}
+
+int rs_build_mesh_bvh(const rs_mesh *m, void *ws, size_t ws_bytes, rs_bvh *out, void *stream)
+{
+    int e = check_mesh(m);
+    if (e) return e;
+    if (!ws || !out || !aligned(ws, 256)) return RS_ERR_INVALID_ARG;
+    if (ws_bytes < make_layout(m->n_tris).total) return RS_ERR_WORKSPACE;
+    e = launch_build_mesh(m, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+    if (e) return e;
+    BvhDesc D{};
+    D.magic = kMagic;
+    D.n = m->n_tris;
+    D.Q = 0.0f;
+    D.root = m->n_tris >= 2 ? 0 : ~0;
+    D.ws = static_cast<char *>(ws);
+    D.ws_bytes = ws_bytes;
+    D.kind = kKindMesh;
+    memset(out, 0, sizeof(*out));
+    memcpy(out, &D, sizeof(D));
+    return RS_OK;
+}
+
+int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
+                  int32_t *tri, void *stream)
+{
+    int e = check_rays(rays);
+    if (e) return e;
+    BvhDesc M;
+    if ((e = check_mesh_bvh(mesh_bvh, nullptr, M))) return e;
+    if (rays->n > 0 && (!t_hit || !tri)) return RS_ERR_INVALID_ARG;
+    return launch_trace_mesh(M, rays, t_limit, any_hit ? 1 : 0, t_hit, tri, static_cast<hipStream_t>(stream));
+}
+
+size_t rs_mesh_frame_bytes(int64_t n_rays) { return n_rays >= 0 ? mesh_frame_bytes(n_rays) : 0; }
+
+int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
+                       const rs_shading *sh, const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame,
+                       void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if ((e = check_rays(rays))) return e;
+    if ((e = check_mesh(m))) return e;
+    if ((e = check_shading(sh))) return e;
+    if (rays->t_max || rays->bg) return RS_ERR_UNSUPPORTED;
+    BvhDesc G, M;
+    if ((e = check_bvh(gauss_bvh, g, p, G))) return e;
+    if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
+    if (rays->n > 0 && (!out_rgb || !frame || !aligned(frame, 256))) return RS_ERR_INVALID_ARG;
+    return launch_mesh_fwd(G, M, g, sh, rays, p, out_rgb, frame, static_cast<hipStream_t>(stream));
+}
+
+int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
+                       const rs_shading *sh, const rs_rays *rays, const rs_params *p, const float *grad_rgb,
+                       void *frame, rs_grads *out, void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if ((e = check_rays(rays))) return e;
+    if ((e = check_mesh(m))) return e;
+    if ((e = check_shading(sh))) return e;
+    if (rays->t_max || rays->bg) return RS_ERR_UNSUPPORTED;
+    BvhDesc G, M;
+    if ((e = check_bvh(gauss_bvh, g, p, G))) return e;
+    if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
+    if (!out) return RS_ERR_INVALID_ARG;
+    if (rays->n > 0 && (!grad_rgb || !frame || !aligned(frame, 256))) return RS_ERR_INVALID_ARG;
+    return launch_mesh_bwd(G, g, rays, p, grad_rgb, frame, out, static_cast<hipStream_t>(stream));
 }
 
 int rs_read_status(const rs_bvh *bvh, void *stream)

@@ -105,6 +105,7 @@ __global__ __launch_bounds__(256) void k_morton(const float *__restrict__ mean, 
     }
     codes[i] = (spread10(q[0]) << 2) | (spread10(q[1]) << 1) | spread10(q[2]);
     vals[i] = uint32_t(i);
+    if (!scale) return;  // triangle centroids: validated elsewhere
     // input validation (sticky device status)
     float s0 = scale[3 * i], s1 = scale[3 * i + 1], s2 = scale[3 * i + 2];
     float q0 = quat[4 * i], q1 = quat[4 * i + 1], q2 = quat[4 * i + 2], q3 = quat[4 * i + 3];
@@ -411,16 +412,82 @@ __global__ __launch_bounds__(256) void k_fill_nodes(const float *__restrict__ le
         for (int k = 0; k < 6; ++k) h->root_box[k] = ibox[k];
 }
 
+// ----------------------------------------------------------- triangle mesh
+
+__device__ inline int32_t clamp_index(int32_t v, int64_t n_verts, WsHeader *h)
+{
+    if (v < 0 || v >= n_verts) {
+        atomicOr(&h->status, kStatusNonfinite);
+        return 0;
+    }
+    return v;
+}
+
+// Triangle centroids (into the record area, before the sort); indices out of
+// range set the status and read vertex 0 instead.
+__global__ __launch_bounds__(256) void k_tri_centroids(const float *__restrict__ verts, const int32_t *__restrict__ tris,
+                                                       int64_t n_tris, int64_t n_verts, float *__restrict__ cent,
+                                                       WsHeader *h)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n_tris) return;
+    float c[3] = {0.0f, 0.0f, 0.0f};
+    for (int k = 0; k < 3; ++k) {
+        const int32_t v = clamp_index(tris[3 * i + k], n_verts, h);
+        for (int a = 0; a < 3; ++a) c[a] += verts[3 * v + a];
+    }
+    for (int a = 0; a < 3; ++a) cent[3 * i + a] = c[a] * (1.0f / 3.0f);
+}
+
+// Triangle records in sorted order: r0 = (v0, e1.x), r1 = (e1.yz, e2.xy),
+// r2 = (e2.z, material bits, triangle index bits, 0), r3 unused; leaf boxes
+// are the vertex bounds rounded outward.
+__global__ __launch_bounds__(256) void k_tri_records(const uint32_t *__restrict__ perm, const float *__restrict__ verts,
+                                                     const int32_t *__restrict__ tris,
+                                                     const int32_t *__restrict__ material, int64_t n_tris,
+                                                     int64_t n_verts, float4 *__restrict__ records,
+                                                     float *__restrict__ leaf_boxes, int32_t *__restrict__ inv,
+                                                     WsHeader *h)
+{
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n_tris) return;
+    const uint32_t i = perm[j];
+    float v[3][3];
+    for (int k = 0; k < 3; ++k) {
+        const int32_t vi = clamp_index(tris[3 * i + k], n_verts, h);
+        for (int a = 0; a < 3; ++a) v[k][a] = verts[3 * vi + a];
+    }
+    const float e1x = v[1][0] - v[0][0], e1y = v[1][1] - v[0][1], e1z = v[1][2] - v[0][2];
+    const float e2x = v[2][0] - v[0][0], e2y = v[2][1] - v[0][1], e2z = v[2][2] - v[0][2];
+    const int32_t mat = material ? material[i] : 0;
+    records[4 * j + 0] = make_float4(v[0][0], v[0][1], v[0][2], e1x);
+    records[4 * j + 1] = make_float4(e1y, e1z, e2x, e2y);
+    records[4 * j + 2] = make_float4(e2z, __int_as_float(mat), __int_as_float(int32_t(i)), 0.0f);
+    records[4 * j + 3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int a = 0; a < 3; ++a) {
+        const float lo = fminf(fminf(v[0][a], v[1][a]), v[2][a]);
+        const float hi = fmaxf(fmaxf(v[0][a], v[1][a]), v[2][a]);
+        const float pad = 1e-6f * (1.0f + fmaxf(fabsf(lo), fabsf(hi)));
+        leaf_boxes[6 * j + a] = lo - pad;
+        leaf_boxes[6 * j + 3 + a] = hi + pad;
+    }
+    inv[i] = int32_t(j);
+}
+
 // ------------------------------------------------------------------- host
 
 static inline int blocks_for(int64_t n, int threads) { return int((n + threads - 1) / threads); }
 
-int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
+// Sort + link + refit shared by the Gaussian and the triangle BVH: `points`
+// are the Morton sites; `records_fn` writes records and leaf boxes in sorted
+// order once the permutation is known.
+template <typename RecordsFn>
+static int build_core(int64_t n, const float *points, const float *scale, const float *quat, const float *opacity,
+                      const float *rgb, char *ws, hipStream_t st, RecordsFn records_fn, bool init_header)
 {
-    const int64_t n = g->n;
     Layout L = make_layout(n);
     WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
-    k_init_header<<<1, 64, 0, st>>>(h);
+    if (init_header) k_init_header<<<1, 64, 0, st>>>(h);
     if (n == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
     uint32_t *codes = reinterpret_cast<uint32_t *>(ws + L.codes);
     uint32_t *vals = reinterpret_cast<uint32_t *>(ws + L.gidx);
@@ -436,8 +503,8 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
     uint32_t *visit = reinterpret_cast<uint32_t *>(ws + L.visit);
 
     int bgrid = blocks_for(n, 256);
-    k_bounds<<<bgrid < 1024 ? bgrid : 1024, 256, 0, st>>>(g->mean, n, h);
-    k_morton<<<bgrid, 256, 0, st>>>(g->mean, g->scale, g->quat, g->opacity, g->rgb, n, h, codes, vals);
+    k_bounds<<<bgrid < 1024 ? bgrid : 1024, 256, 0, st>>>(points, n, h);
+    k_morton<<<bgrid, 256, 0, st>>>(points, scale, quat, opacity, rgb, n, h, codes, vals);
     // 4 passes of 8 bits: A -> B -> A -> B -> A
     uint32_t *ka = codes, *va = vals, *kb = kalt, *vb = valt;
     int64_t nb = L.sort_blocks;
@@ -451,7 +518,7 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
         t = ka; ka = kb; kb = t;
         t = va; va = vb; vb = t;
     }
-    k_records<<<bgrid, 256, 0, st>>>(vals, g->mean, g->scale, g->quat, g->opacity, n, Q, records, leaf_boxes, inv);
+    records_fn(vals, records, leaf_boxes, inv, h);
     if (n >= 2) {
         k_fill_u32<<<blocks_for(L.n_int, 256) < 2048 ? blocks_for(L.n_int, 256) : 2048, 256, 0, st>>>(visit, L.n_int,
                                                                                                        0u);
@@ -464,6 +531,33 @@ int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
         (void)hipMemcpyAsync(h->root_box, leaf_boxes, 6 * sizeof(float), hipMemcpyDeviceToDevice, st);
     }
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
+{
+    const int64_t n = g->n;
+    const int bgrid = blocks_for(n, 256);
+    auto rec = [&](const uint32_t *perm, float4 *records, float *leaf_boxes, int32_t *inv, WsHeader *) {
+        k_records<<<bgrid, 256, 0, st>>>(perm, g->mean, g->scale, g->quat, g->opacity, n, Q, records, leaf_boxes, inv);
+    };
+    return build_core(n, g->mean, g->scale, g->quat, g->opacity, g->rgb, ws, st, rec, true);
+}
+
+int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st)
+{
+    const int64_t n = m->n_tris;
+    Layout L = make_layout(n);
+    WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
+    k_init_header<<<1, 64, 0, st>>>(h);
+    if (n == 0) return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+    const int bgrid = blocks_for(n, 256);
+    float *cent = reinterpret_cast<float *>(ws + L.records);  // overwritten by the records afterwards
+    k_tri_centroids<<<bgrid, 256, 0, st>>>(m->verts, m->tris, n, m->n_verts, cent, h);
+    auto rec = [&](const uint32_t *perm, float4 *records, float *leaf_boxes, int32_t *inv, WsHeader *hh) {
+        k_tri_records<<<bgrid, 256, 0, st>>>(perm, m->verts, m->tris, m->material, n, m->n_verts, records, leaf_boxes,
+                                             inv, hh);
+    };
+    return build_core(n, cent, nullptr, nullptr, nullptr, nullptr, ws, st, rec, false);
 }
 
 }  // namespace rs

@@ -88,8 +88,12 @@ struct BvhDesc {
     int32_t root;       // root ref (0: internal node 0; ~0: single leaf; unused when n == 0)
     char *ws;
     uint64_t ws_bytes;
-    uint64_t pad[10];
+    int32_t kind;       // kKindGaussians or kKindMesh
+    int32_t pad0;
+    uint64_t pad[9];
 };
+constexpr int32_t kKindGaussians = 1;
+constexpr int32_t kKindMesh = 2;
 static_assert(sizeof(BvhDesc) <= sizeof(rs_bvh), "descriptor size");
 
 // ---------------------------------------------------------------- helpers
@@ -116,5 +120,31 @@ __device__ inline uint64_t make_key(float t1, uint32_t gid)
 __device__ inline float key_t(uint64_t k) { return ordered_to_float(uint32_t(k >> 32)); }
 
 constexpr uint64_t kKeyNone = ~0ull;
+
+// Host description of one ray set of a render launch.
+struct SetDesc {
+    const rs_rays *rays;
+    float *out_rgb;
+    void *state;
+    const float *grad;
+    float bg[3];
+    int32_t zero_colour;
+};
+
+int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st);
+int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets, bool bwd,
+                hipStream_t st);
+int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
+                  void *state, const float *grad, const rs_grads *grads, hipStream_t st);
+void zero_gacc(const BvhDesc &D, hipStream_t st);
+int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st);
+int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
+                      int32_t *tri, hipStream_t st);
+size_t mesh_frame_bytes(int64_t n);
+int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,
+                    const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame, hipStream_t st);
+int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                    const float *grad, void *frame, const rs_grads *grads, hipStream_t st);
+void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st);
 
 }  // namespace rs

@@ -22,65 +22,30 @@
 // summed across lanes before one set of float32 atomics per Gaussian.
 #include <math.h>
 
-#include "rs_internal.h"
+#include "rs_device.h"
 
 #pragma clang fp contract(on)
 
 namespace rs {
 
-struct ViewEntry {
-    int64_t ray_offset;
-    int64_t first_packet;
-    int32_t width, height, tiles_x, pad;
-};
-
 struct RenderParams {
-    int64_t n_rays;
-    int64_t n_packets;
+    int64_t n_packets;         // all sets
+    int64_t packets_per_set;   // every set has the same ray layout (views / packets)
+    int64_t n_rays;            // rays per set
     int64_t n_gauss;
     int32_t root;
     int32_t stack_depth;
     float Q, eps1, t_min;
     int32_t max_hits;
-    float bg[3];
     uint32_t flags;
     int32_t persistent;
     int32_t brute;
-    int32_t zero_colour;
     int32_t count;
     int32_t n_views;
     ViewEntry views[RS_MAX_VIEWS];
 };
 
-constexpr float kInf = __builtin_huge_valf();
-
-// --------------------------------------------------------------- packets
-
-// Packet index -> ray index of this lane (8x8 tiles within each view).
-__device__ inline int64_t packet_ray(const RenderParams &P, int64_t pkt, int lane, bool &valid)
-{
-    if (P.n_views == 0) {
-        int64_t r = pkt * kWave + lane;
-        valid = r < P.n_rays;
-        return r;
-    }
-    int v = 0;
-    for (int k = 1; k < P.n_views; ++k)
-        if (pkt >= P.views[k].first_packet) v = k;
-    const ViewEntry &V = P.views[v];
-    int64_t local = pkt - V.first_packet;
-    int64_t ty = local / V.tiles_x, tx = local - ty * V.tiles_x;
-    int64_t x = tx * kTile + (lane & (kTile - 1));
-    int64_t y = ty * kTile + (lane / kTile);
-    valid = x < V.width && y < V.height;
-    return V.ray_offset + y * V.width + x;
-}
-
 // ------------------------------------------------------------ intersection
-
-struct Ray {
-    float ox, oy, oz, dx, dy, dz;
-};
 
 // Ray / confidence-ellipsoid test (Sec. 3, Prop. 1, Prop. 2) for the record
 // r0..r3 (R^T, 1/s, mean, opacity). With x = o - m, the whitened ray is
@@ -305,28 +270,24 @@ __device__ inline float wave_sum16_transposed(const float (&in)[16], int lane)
 
 // ----------------------------------------------------------------- kernel
 
-struct Ptrs {
-    const float *quat, *rgb, *origin, *dir, *tmax, *bgray, *grad;
+// One set of rays traced by a launch: its rays, optional per-ray limit and
+// background, outputs (forward) or upstream gradient and saved state (adjoint).
+struct RaySet {
+    const float *origin, *dir, *tmax, *bgray, *grad;
     float *out_rgb;
     float4 *state;
-    float *d_mean, *d_scale, *d_quat, *d_opacity, *d_rgb;
+    float bg[3];
+    int32_t zero_colour;
+};
+
+struct Ptrs {
+    const float *quat, *rgb;
+    RaySet set[2];
     int32_t *status;
     uint32_t *queue;
     unsigned long long *counters;
     float *gacc;  // adjoint accumulator, 16 floats per Gaussian (see k_scatter_grads)
 };
-
-// Slab-test constants: a box [lo, hi] is entered at max_k (near_k - o_k) / d_k and
-// left at min_k (far_k - o_k) / d_k, evaluated as fma(plane, 1/d, -o/d). The far
-// distance and the round's upper bound are widened by a relative 2^-19 plus the
-// rounding scale of o/d, so rounding never culls a box the exact test keeps.
-constexpr float kWiden = 1.9073486328125e-6f;  // 2^-19
-
-struct Slab {
-    float ix, iy, iz, nx, ny, nz, pad;
-};
-
-__device__ inline float widen(float t, float pad) { return __builtin_fmaf(fabsf(t), kWiden, t) + pad; }
 
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
 // (512 / waves): the adjoint carries the gradient temporaries as well.
@@ -366,59 +327,44 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         if (pkt >= P.n_packets) break;
         ++c_pkt;
 
+        // the packet's ray set (uniform) and its packet index within the set
+        const int si = pkt >= P.packets_per_set ? 1 : 0;
+        const RaySet &S = ptr.set[si];
+        const bool zc = S.zero_colour != 0;
         bool valid;
-        const int64_t ray_id = packet_ray(P, pkt, lane, valid);
+        const int64_t ray_id = packet_ray(P, pkt - si * P.packets_per_set, lane, valid);
         Ray ray;
-        float tmax = kInf, bgr = P.bg[0], bgg = P.bg[1], bgb = P.bg[2];
+        float tmax = kInf, bgr = S.bg[0], bgg = S.bg[1], bgb = S.bg[2];
         if (valid) {
-            ray.ox = ptr.origin[3 * ray_id];
-            ray.oy = ptr.origin[3 * ray_id + 1];
-            ray.oz = ptr.origin[3 * ray_id + 2];
-            ray.dx = ptr.dir[3 * ray_id];
-            ray.dy = ptr.dir[3 * ray_id + 1];
-            ray.dz = ptr.dir[3 * ray_id + 2];
-            if (ptr.tmax) tmax = ptr.tmax[ray_id];
-            if (ptr.bgray) {
-                bgr = ptr.bgray[3 * ray_id];
-                bgg = ptr.bgray[3 * ray_id + 1];
-                bgb = ptr.bgray[3 * ray_id + 2];
+            ray.ox = S.origin[3 * ray_id];
+            ray.oy = S.origin[3 * ray_id + 1];
+            ray.oz = S.origin[3 * ray_id + 2];
+            ray.dx = S.dir[3 * ray_id];
+            ray.dy = S.dir[3 * ray_id + 1];
+            ray.dz = S.dir[3 * ray_id + 2];
+            if (S.tmax) tmax = S.tmax[ray_id];
+            if (S.bgray) {
+                bgr = S.bgray[3 * ray_id];
+                bgg = S.bgray[3 * ray_id + 1];
+                bgb = S.bgray[3 * ray_id + 2];
             }
         } else {
             ray.ox = ray.oy = ray.oz = 0.0f;
             ray.dx = ray.dy = 0.0f;
             ray.dz = 1.0f;
         }
-        // slab constants (zero direction components replaced by a tiny value of the same sign)
-        Slab sl;
-        {
-            const float sx = fabsf(ray.dx) > 1e-20f ? ray.dx : copysignf(1e-20f, ray.dx);
-            const float sy = fabsf(ray.dy) > 1e-20f ? ray.dy : copysignf(1e-20f, ray.dy);
-            const float sz = fabsf(ray.dz) > 1e-20f ? ray.dz : copysignf(1e-20f, ray.dz);
-            sl.ix = 1.0f / sx;
-            sl.iy = 1.0f / sy;
-            sl.iz = 1.0f / sz;
-            sl.nx = -ray.ox * sl.ix;
-            sl.ny = -ray.oy * sl.iy;
-            sl.nz = -ray.oz * sl.iz;
-            sl.pad = kWiden * fmaxf(fmaxf(fabsf(sl.nx), fabsf(sl.ny)), fabsf(sl.nz));
-        }
-        // when every valid lane's direction has the same sign per axis, the near and far
-        // planes of a box are chosen once per wave (scalar selects)
-        const uint64_t vmask = __ballot(valid);
-        const uint64_t bx = __ballot(valid && sl.ix >= 0.0f), by = __ballot(valid && sl.iy >= 0.0f),
-                       bz = __ballot(valid && sl.iz >= 0.0f);
-        const bool uni = (bx == 0 || bx == vmask) && (by == 0 || by == vmask) && (bz == 0 || bz == vmask);
-        const bool px = bx != 0, py = by != 0, pz = bz != 0;
+        const Slab sl = make_slab(ray);
+        const WaveSigns wsg = wave_signs(sl, valid);
 
         Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
-        bool live = valid && P.n_gauss > 0;
+        bool live = valid && P.n_gauss > 0 && tmax > P.t_min;
         uint64_t last = 0;  // keys of this round must exceed it
         float gr = 0.0f, gg = 0.0f, gb = 0.0f, Cor = 0.0f, Cog = 0.0f, Cob = 0.0f;
         if (BWD && valid) {
-            gr = ptr.grad[3 * ray_id];
-            gg = ptr.grad[3 * ray_id + 1];
-            gb = ptr.grad[3 * ray_id + 2];
-            const float4 s = ptr.state[ray_id];
+            gr = S.grad[3 * ray_id];
+            gg = S.grad[3 * ray_id + 1];
+            gb = S.grad[3 * ray_id + 2];
+            const float4 s = S.state[ray_id];
             Cor = s.x;
             Cog = s.y;
             Cob = s.z;
@@ -473,33 +419,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                         const int64_t ns = __builtin_amdgcn_readfirstlane(node);
                         const float4 n0 = nodes[4 * ns], n1 = nodes[4 * ns + 1], n2 = nodes[4 * ns + 2],
                                      n3 = nodes[4 * ns + 3];
-                        // child boxes: L = (n0.xyz, n0.w n1.xy), R = (n1.zw n2.x, n2.yzw)
                         float ln, lf, rn, rf;
-                        if (uni) {
-                            ln = fmaxf(fmaxf(__builtin_fmaf(px ? n0.x : n0.w, sl.ix, sl.nx),
-                                             __builtin_fmaf(py ? n0.y : n1.x, sl.iy, sl.ny)),
-                                       __builtin_fmaf(pz ? n0.z : n1.y, sl.iz, sl.nz));
-                            lf = fminf(fminf(__builtin_fmaf(px ? n0.w : n0.x, sl.ix, sl.nx),
-                                             __builtin_fmaf(py ? n1.x : n0.y, sl.iy, sl.ny)),
-                                       __builtin_fmaf(pz ? n1.y : n0.z, sl.iz, sl.nz));
-                            rn = fmaxf(fmaxf(__builtin_fmaf(px ? n1.z : n2.y, sl.ix, sl.nx),
-                                             __builtin_fmaf(py ? n1.w : n2.z, sl.iy, sl.ny)),
-                                       __builtin_fmaf(pz ? n2.x : n2.w, sl.iz, sl.nz));
-                            rf = fminf(fminf(__builtin_fmaf(px ? n2.y : n1.z, sl.ix, sl.nx),
-                                             __builtin_fmaf(py ? n2.z : n1.w, sl.iy, sl.ny)),
-                                       __builtin_fmaf(pz ? n2.w : n2.x, sl.iz, sl.nz));
-                        } else {
-                            const float lx0 = __builtin_fmaf(n0.x, sl.ix, sl.nx), lx1 = __builtin_fmaf(n0.w, sl.ix, sl.nx);
-                            const float ly0 = __builtin_fmaf(n0.y, sl.iy, sl.ny), ly1 = __builtin_fmaf(n1.x, sl.iy, sl.ny);
-                            const float lz0 = __builtin_fmaf(n0.z, sl.iz, sl.nz), lz1 = __builtin_fmaf(n1.y, sl.iz, sl.nz);
-                            const float rx0 = __builtin_fmaf(n1.z, sl.ix, sl.nx), rx1 = __builtin_fmaf(n2.y, sl.ix, sl.nx);
-                            const float ry0 = __builtin_fmaf(n1.w, sl.iy, sl.ny), ry1 = __builtin_fmaf(n2.z, sl.iy, sl.ny);
-                            const float rz0 = __builtin_fmaf(n2.x, sl.iz, sl.nz), rz1 = __builtin_fmaf(n2.w, sl.iz, sl.nz);
-                            ln = fmaxf(fmaxf(fminf(lx0, lx1), fminf(ly0, ly1)), fminf(lz0, lz1));
-                            lf = fminf(fminf(fmaxf(lx0, lx1), fmaxf(ly0, ly1)), fmaxf(lz0, lz1));
-                            rn = fmaxf(fmaxf(fminf(rx0, rx1), fminf(ry0, ry1)), fminf(rz0, rz1));
-                            rf = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1));
-                        }
+                        child_slabs(n0, n1, n2, sl, wsg, ln, lf, rn, rf);
                         const bool hl = live && fmaxf(ln, t_lo) <= fminf(widen(lf, sl.pad), t_hi_w);
                         const bool hr = live && fmaxf(rn, t_lo) <= fminf(widen(rf, sl.pad), t_hi_w);
                         const uint64_t bl = __ballot(hl), br = __ballot(hr);
@@ -568,7 +489,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                     float t1, h2;
                     ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2);
                     al = r3.w * __expf(-0.5f * h2);
-                    if (!P.zero_colour) {
+                    if (!zc) {
                         cr = ptr.rgb[3 * gid];
                         cg = ptr.rgb[3 * gid + 1];
                         cb = ptr.rgb[3 * gid + 2];
@@ -592,9 +513,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                         }
                         grad_hit(ray, r0, r1, r2, r3, ptr.quat, gid, dLda, al, G);
                         const float wgt = al * Tk;
-                        G.v[11] = P.zero_colour ? 0.0f : gr * wgt;
-                        G.v[12] = P.zero_colour ? 0.0f : gg * wgt;
-                        G.v[13] = P.zero_colour ? 0.0f : gb * wgt;
+                        G.v[11] = zc ? 0.0f : gr * wgt;
+                        G.v[12] = zc ? 0.0f : gg * wgt;
+                        G.v[13] = zc ? 0.0f : gb * wgt;
                     }
                     // wave aggregation: for each distinct Gaussian among the active lanes, the
                     // lanes holding it are summed (transposed butterfly) and one 14-lane atomic
@@ -625,10 +546,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         }
 
         if (!BWD && valid) {
-            ptr.out_rgb[3 * ray_id] = __builtin_fmaf(A.T, bgr, A.Cr);
-            ptr.out_rgb[3 * ray_id + 1] = __builtin_fmaf(A.T, bgg, A.Cg);
-            ptr.out_rgb[3 * ray_id + 2] = __builtin_fmaf(A.T, bgb, A.Cb);
-            if (ptr.state) ptr.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
+            S.out_rgb[3 * ray_id] = __builtin_fmaf(A.T, bgr, A.Cr);
+            S.out_rgb[3 * ray_id + 1] = __builtin_fmaf(A.T, bgg, A.Cg);
+            S.out_rgb[3 * ray_id + 2] = __builtin_fmaf(A.T, bgb, A.Cb);
+            if (S.state) S.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
                                                            __builtin_fmaf(A.T, bgg, A.Cg),
                                                            __builtin_fmaf(A.T, bgb, A.Cb), A.T);
         }
@@ -658,8 +579,7 @@ __global__ void k_zero_f32(float *p, int64_t n)
 // Accumulator (16 floats per Gaussian: mean 3, scale 3, quat 4, opacity 1,
 // rgb 3, 2 unused) -> the caller's gradient arrays.
 __global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict__ gacc, int64_t n, float *d_mean,
-                                                       float *d_scale, float *d_quat, float *d_opacity, float *d_rgb,
-                                                       int zero_colour)
+                                                       float *d_scale, float *d_quat, float *d_opacity, float *d_rgb)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -677,9 +597,9 @@ __global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict_
     if (d_quat) reinterpret_cast<float4 *>(d_quat)[i] = make_float4(b.z, b.w, c.x, c.y);
     if (d_opacity) d_opacity[i] = c.z;
     if (d_rgb) {
-        d_rgb[3 * i] = zero_colour ? 0.0f : c.w;
-        d_rgb[3 * i + 1] = zero_colour ? 0.0f : d.x;
-        d_rgb[3 * i + 2] = zero_colour ? 0.0f : d.y;
+        d_rgb[3 * i] = c.w;
+        d_rgb[3 * i + 1] = d.x;
+        d_rgb[3 * i + 2] = d.y;
     }
 }
 
@@ -713,13 +633,29 @@ static void launch_k(bool bwd, int grid, const float4 *records, const float4 *no
     }
 }
 
-int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
-                  float *out_rgb, void *state, const float *grad, const rs_grads *grads, hipStream_t st)
+void zero_gacc(const BvhDesc &D, hipStream_t st)
 {
-    const bool bwd = grad != nullptr;
+    Layout L = make_layout(D.n);
+    zero(reinterpret_cast<float *>(D.ws + L.gacc), 16 * D.n, st);
+}
+
+void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st)
+{
+    if (D.n <= 0) return;
+    Layout L = make_layout(D.n);
+    k_scatter_grads<<<int((D.n + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(D.ws + L.gacc), D.n,
+                                                             grads->d_mean, grads->d_scale, grads->d_quat,
+                                                             grads->d_opacity, grads->d_rgb);
+}
+
+// One launch over one or two ray sets sharing a layout (same count, same views).
+int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets,
+                bool bwd, hipStream_t st)
+{
     Layout L = make_layout(D.n);
     char *ws = D.ws;
     WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
+    const rs_rays *rays = sets[0].rays;
 
     RenderParams P{};
     P.n_rays = rays->n;
@@ -730,11 +666,9 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     P.eps1 = p->eps1;
     P.t_min = p->t_min;
     P.max_hits = p->max_hits;
-    for (int k = 0; k < 3; ++k) P.bg[k] = p->bg[k];
     P.flags = p->flags;
     P.persistent = (p->flags & RS_PERSISTENT) ? 1 : 0;
     P.brute = (p->flags & RS_BRUTE_FORCE) ? 1 : 0;
-    P.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
     P.count = (p->flags & RS_COUNTERS) ? 1 : 0;
     P.n_views = rays->n_views;
     int64_t packets = 0;
@@ -752,50 +686,48 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
             packets += int64_t(E.tiles_x) * ((V.height + kTile - 1) / kTile);
         }
     }
-    P.n_packets = packets;
+    P.packets_per_set = packets;
+    P.n_packets = packets * nsets;
 
     Ptrs ptr{};
     ptr.quat = g->quat;
     ptr.rgb = g->rgb;
-    ptr.origin = rays->origin;
-    ptr.dir = rays->dir;
-    ptr.tmax = rays->t_max;
-    ptr.bgray = rays->bg;
-    ptr.grad = grad;
-    ptr.out_rgb = out_rgb;
-    ptr.state = reinterpret_cast<float4 *>(state);
-    if (bwd && grads) {
-        ptr.d_mean = grads->d_mean;
-        ptr.d_scale = grads->d_scale;
-        ptr.d_quat = grads->d_quat;
-        ptr.d_opacity = grads->d_opacity;
-        ptr.d_rgb = grads->d_rgb;
-        ptr.gacc = reinterpret_cast<float *>(ws + L.gacc);
-        zero(ptr.gacc, 16 * g->n, st);
+    for (int k = 0; k < 2; ++k) {
+        const SetDesc &E = sets[k < nsets ? k : 0];
+        RaySet &R = ptr.set[k];
+        R.origin = E.rays->origin;
+        R.dir = E.rays->dir;
+        R.tmax = E.rays->t_max;
+        R.bgray = E.rays->bg;
+        R.grad = E.grad;
+        R.out_rgb = E.out_rgb;
+        R.state = reinterpret_cast<float4 *>(E.state);
+        for (int c = 0; c < 3; ++c) R.bg[c] = E.bg[c];
+        R.zero_colour = E.zero_colour;
     }
     ptr.status = &h->status;
     ptr.queue = &h->queue;
     ptr.counters = reinterpret_cast<unsigned long long *>(h->counters);
+    ptr.gacc = reinterpret_cast<float *>(ws + L.gacc);
 
-    if (packets > 0) {
-
+    if (P.n_packets > 0) {
         int grid;
         if (P.persistent) {
             k_zero_queue<<<1, 64, 0, st>>>(&h->queue);
             int dev = 0, cus = 256;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
-            grid = int(waves < packets ? waves : packets);
+            const int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
+            grid = int(waves < P.n_packets ? waves : P.n_packets);
         } else {
-            grid = int(packets);
+            grid = int(P.n_packets);
         }
         const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
         const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
         const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
         const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
         // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
-        // the default is the fastest measured size of each pass on MI355X
+        // the default is the fastest measured size on MI355X
         const int K = p->kbuf > 0 ? p->kbuf : 24;
         switch (K) {
         case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
@@ -805,10 +737,24 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
         default: return RS_ERR_INVALID_ARG;
         }
     }
-    if (bwd && g->n > 0)
-        k_scatter_grads<<<int((g->n + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(ptr.gacc), g->n,
-                                                                  ptr.d_mean, ptr.d_scale, ptr.d_quat, ptr.d_opacity,
-                                                                  ptr.d_rgb, P.zero_colour);
+    return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+                  float *out_rgb, void *state, const float *grad, const rs_grads *grads, hipStream_t st)
+{
+    const bool bwd = grad != nullptr;
+    SetDesc S{};
+    S.rays = rays;
+    S.out_rgb = out_rgb;
+    S.state = state;
+    S.grad = grad;
+    for (int c = 0; c < 3; ++c) S.bg[c] = p->bg[c];
+    S.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
+    if (bwd) zero_gacc(D, st);
+    int e = launch_sets(D, g, p, 1, &S, bwd, st);
+    if (e) return e;
+    if (bwd) scatter_gacc(D, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 

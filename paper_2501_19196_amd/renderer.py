@@ -191,6 +191,121 @@ def download(bvh: BVH):
                 bounds=bounds)
 
 
+# ------------------------------------------------------------ mesh + Gaussians
+
+@dataclass
+class Mesh:
+    verts: torch.Tensor            # [V, 3] float32
+    tris: torch.Tensor             # [T, 3] int32
+    material: torch.Tensor = None  # [T] int32, 1 mirror / 0 diffuse
+
+    def c(self):
+        _dev(self.verts, "verts")
+        _dev(self.tris, "tris", torch.int32)
+        if self.material is not None:
+            _dev(self.material, "material", torch.int32)
+        return L.rs_mesh(int(self.verts.shape[0]), int(self.tris.shape[0]), _ptr(self.verts), _ptr(self.tris),
+                         _ptr(self.material))
+
+    @property
+    def n(self):
+        return int(self.tris.shape[0])
+
+
+@dataclass
+class Shading:
+    light: tuple = (2.0, -2.0, 5.0)
+    intensity: float = 1.0
+    albedo: float = 0.8
+    mirror_reflectance: float = 0.8
+    mirror_diffuse: float = 0.2
+    offset: float = 1e-4
+
+    def c(self):
+        s = L.rs_shading()
+        for k in range(3):
+            s.light[k] = float(self.light[k])
+        s.intensity, s.albedo = float(self.intensity), float(self.albedo)
+        s.mirror_reflectance, s.mirror_diffuse = float(self.mirror_reflectance), float(self.mirror_diffuse)
+        s.offset = float(self.offset)
+        return s
+
+
+def build_mesh_bvh(mesh: Mesh, workspace=None):
+    lib = L.lib()
+    nbytes = workspace_bytes(mesh.n)
+    if workspace is None or workspace.numel() < nbytes:
+        workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=mesh.verts.device)
+    desc = L.rs_bvh()
+    mc = mesh.c()
+    L.check(lib.rs_build_mesh_bvh(C.byref(mc), _ptr(workspace), C.c_size_t(workspace.numel()), C.byref(desc),
+                                  _stream()), "rs_build_mesh_bvh")
+    return BVH(mesh.n, 0.0, workspace, desc)
+
+
+def trace_mesh(mbvh: BVH, rays: Rays, t_limit=None, any_hit=False):
+    n = rays.n
+    t = torch.empty(n, dtype=torch.float32, device=rays.origin.device)
+    tri = torch.empty(n, dtype=torch.int32, device=rays.origin.device)
+    rc = rays.c()
+    L.check(L.lib().rs_trace_mesh(C.byref(mbvh.desc), C.byref(rc), _ptr(t_limit), int(any_hit), _ptr(t), _ptr(tri),
+                                  _stream()), "rs_trace_mesh")
+    return t, tri
+
+
+def mesh_frame(n, device="cuda"):
+    return torch.empty(max(int(L.lib().rs_mesh_frame_bytes(int(n))), 256), dtype=torch.uint8, device=device)
+
+
+def render_mesh_fwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Shading, rays: Rays, params: Params,
+                    out=None, frame=None):
+    n = rays.n
+    if out is None:
+        out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
+    if frame is None:
+        frame = mesh_frame(n, rays.origin.device)
+    gc, mc, sc, rc, pc = g.c(), mesh.c(), shading.c(), rays.c(), params.c()
+    L.check(L.lib().rs_render_mesh_fwd(C.byref(gbvh.desc), C.byref(mbvh.desc), C.byref(gc), C.byref(mc), C.byref(sc),
+                                       C.byref(rc), C.byref(pc), _ptr(out), _ptr(frame), _stream()),
+            "rs_render_mesh_fwd")
+    return out, frame
+
+
+def render_mesh_bwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Shading, rays: Rays, params: Params,
+                    grad_rgb, frame, grads=None):
+    grad_rgb = _dev(grad_rgb.contiguous(), "grad_rgb")
+    if grads is None:
+        grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
+                 torch.empty_like(g.opacity), torch.empty_like(g.rgb))
+    gr = L.rs_grads(*[_ptr(t) for t in grads])
+    gc, mc, sc, rc, pc = g.c(), mesh.c(), shading.c(), rays.c(), params.c()
+    L.check(L.lib().rs_render_mesh_bwd(C.byref(gbvh.desc), C.byref(mbvh.desc), C.byref(gc), C.byref(mc), C.byref(sc),
+                                       C.byref(rc), C.byref(pc), _ptr(grad_rgb), _ptr(frame), C.byref(gr),
+                                       _stream()), "rs_render_mesh_bwd")
+    return grads
+
+
+class MeshRender(torch.autograd.Function):
+    """Gaussians + triangle mesh with mirror reflections and shadows; the
+    Gaussian BVH is rebuilt every forward, the mesh BVH is given."""
+
+    @staticmethod
+    def forward(ctx, mean, scale, quat, opacity, rgb, origin, direction, mesh, mbvh, shading, params, views):
+        g = Gaussians(mean.contiguous(), scale.contiguous(), quat.contiguous(), opacity.contiguous(),
+                      rgb.contiguous())
+        rays = Rays(origin.contiguous(), direction.contiguous(), views=list(views or []))
+        gbvh = build_bvh(g, params)
+        out, frame = render_mesh_fwd(gbvh, mbvh, g, mesh, shading, rays, params)
+        ctx.saved = (gbvh, mbvh, g, mesh, shading, rays, params, frame)
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        gbvh, mbvh, g, mesh, shading, rays, params, frame = ctx.saved
+        dm, ds, dq, do, dc = render_mesh_bwd(gbvh, mbvh, g, mesh, shading, rays, params, grad_out.contiguous(), frame)
+        return dm, ds, dq, do, dc, None, None, None, None, None, None, None
+
+
 class RaySplatsRender(torch.autograd.Function):
     """rgb = render(mean, scale, quat, opacity, rgb; rays). The BVH is rebuilt
     in every forward (the parameters change every optimisation step); the
