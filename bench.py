@@ -1,12 +1,20 @@
 """Benchmark of the ray-traced Gaussian renderer on one MI355X.
 
-A step is one pass of the whole hot path over the scene-scale workload
-(1M Gaussians, one 1920x1080 view): BVH rebuild (preprocess, Morton codes,
-radix sort, Karras link, refit), forward render, an L1 loss against a fixed
-target image, and the adjoint render producing gradients for all five
-parameter groups. Inputs are resident in HBM before the timed region.
+A step is one pass of the whole hot path over one workload: BVH rebuild
+(preprocess, Morton codes, radix sort, Karras link, refit), forward render,
+an L1 loss against a fixed target image, and the adjoint render producing
+gradients for all five parameter groups. Inputs are resident in HBM before the
+timed region. The default workload is the scene-scale one (1M Gaussians, one
+1920x1080 view); --workload 3 (8 views) also times one launch per view against
+the batched launch, --workload 5 runs the mesh path (reflection and shadow
+rays).
 
-Prints one JSON line. `value` is forward+backward throughput in Mrays/s.
+The launch shape (hit-buffer size, grid form, packet tile) is autotuned on the
+workload before timing unless --no-autotune; the timed steps replay a HIP
+graph of the step unless --no-graph (the eager step is timed as well).
+
+Prints one JSON line. `value` is forward+backward throughput in Mrays/s
+(primary rays).
 """
 
 import argparse
@@ -20,15 +28,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s fwd and fwd+bwd at 1M Gaussians, % HBM roofline, vs oracle error"
 
+# Algorithmic FP32 work of the render kernels per unit of the library's work
+# counters (an FMA is 2, min/max/compare/rcp/sqrt/exp are 1):
+FLOPS_CHILD = 22.0      # child-box slab test whose box the lane's ray overlaps
+FLOPS_LEAF = 90.0       # ray / ellipsoid test of a live lane at a visited leaf
+FLOPS_COMPOSITE = 110.0  # composited hit (alpha recomputed + Eq. 3 step)
+FLOPS_ADJOINT = 265.0    # adjoint of a composited hit (dL/dalpha + App. A.6)
+
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=4)
-    ap.add_argument("--kbuf", type=int, default=0)
-    ap.add_argument("--persistent", action="store_true")
+    ap.add_argument("--workload", type=int, default=4, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--kbuf", type=int, default=0, help="fixed hit-buffer size (implies --no-autotune)")
+    ap.add_argument("--persistent", action="store_true", help="persistent grid (implies --no-autotune)")
+    ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=8000)
     ap.add_argument("--parity-rays", type=int, default=256)
@@ -36,6 +54,10 @@ def parse():
                     help="one warm-up and one step, then a 256 MiB device copy that calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters; prints no JSON line")
     return ap.parse_args()
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def main():
@@ -49,6 +71,7 @@ def main():
 
     from synthetic import workload
     from synthetic.cameras import concat_rays
+    from synthetic.scenes import jittered_target
     from paper_2501_19196_amd import renderer as R
 
     t0 = time.time()
@@ -56,26 +79,46 @@ def main():
     sc = w["scene"]
     o, d, views = concat_rays(w["cams"])
     views = [tuple(int(x) for x in v) for v in views]
-    target_scene = w.get("target")
-    print(f"[bench] workload {w['name']}: {sc.n} Gaussians, {o.shape[0]} rays (setup {time.time() - t0:.1f}s)",
-          file=sys.stderr, flush=True)
+    mesh_np = w.get("mesh")
+    log(f"workload {w['name']}: {sc.n} Gaussians, {o.shape[0]} rays, {len(views)} views"
+        f"{', mesh %d triangles' % mesh_np.n_tris if mesh_np is not None else ''} (setup {time.time() - t0:.1f}s)")
 
     dev = torch.device("cuda:0")
     t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     g = R.Gaussians(*(t(a) for a in sc.arrays()))
     rays = R.Rays(t(o), t(d), views=views)
-    flags = R.Params().flags | (2 if args.persistent else 0)
-    p = R.Params(kbuf=args.kbuf, flags=flags)
+    fixed = args.kbuf or args.persistent or args.tile_width
+    base = R.Params(kbuf=args.kbuf, flags=2 if args.persistent else 0, tile_width=args.tile_width)
     nr = o.shape[0]
     n = sc.n
 
+    shading = None
+    dm = mbvh = None
+    if mesh_np is not None:
+        dm = R.Mesh(t(mesh_np.verts), t(mesh_np.tris), t(mesh_np.mirror))
+        mbvh = R.build_mesh_bvh(dm)
+        L = w["light"]
+        shading = R.Shading(light=(float(L[0]), float(L[1]), float(L[2])))
+    frame = R.mesh_frame(nr) if mesh_np is not None else None
+
+    def render(bvh, gs, p, out, state=None):
+        if mesh_np is not None:
+            R.render_mesh_fwd(bvh, mbvh, gs, dm, shading, rays, p, out=out, frame=frame)
+        else:
+            R.render_fwd(bvh, gs, rays, p, out=out, state=state)
+
+    def adjoint(bvh, p, grad, state):
+        if mesh_np is not None:
+            R.render_mesh_bwd(bvh, mbvh, g, dm, shading, rays, p, grad, frame, grads=grads)
+        else:
+            R.render_bwd(bvh, g, rays, p, grad, state, grads=grads)
+
     # fixed target: the scene rendered with means jittered by N(0, 0.01)
-    from synthetic.scenes import jittered_target
-    tsc = target_scene or jittered_target(sc, seed=2, sigma=0.01)
+    tsc = w.get("target") or jittered_target(sc, seed=2, sigma=0.01)
     tg = R.Gaussians(*(t(a) for a in tsc.arrays()))
-    tb = R.build_bvh(tg, p)
-    target, _ = R.render_fwd(tb, tg, rays, p, want_state=False)
-    del tb, tg
+    target = torch.empty((nr, 3), dtype=torch.float32, device=dev)
+    render(R.build_bvh(tg, base), tg, base, target)
+    del tg
 
     ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device=dev)
     out = torch.empty((nr, 3), dtype=torch.float32, device=dev)
@@ -83,102 +126,155 @@ def main():
     grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
              torch.empty_like(g.opacity), torch.empty_like(g.rgb))
     ev = lambda: torch.cuda.Event(enable_timing=True)
+
+    # ---- launch shape: autotuned on this workload (plain render form)
+    pf = pb = base
+    tune = None
+    if not fixed and not args.no_autotune and not args.profile:
+        bvh = R.build_bvh(g, base, workspace=ws)
+        R.render_fwd(bvh, g, rays, base, out=out, state=state)
+        gr = torch.sign(out - target) * (1.0 / (3.0 * nr))
+        t1 = time.time()
+        pf, pb, rows = R.autotune(bvh, g, rays, base, grad_rgb=gr, reps=2)
+        tune = dict(fwd=dict(kbuf=pf.kbuf, persistent=bool(pf.flags & 2), tile_width=pf.tile_width),
+                    bwd=dict(kbuf=pb.kbuf, persistent=bool(pb.flags & 2), tile_width=pb.tile_width),
+                    candidates=len(rows), seconds=round(time.time() - t1, 2))
+        log("autotune", tune)
+
     kt = {"build": [], "fwd": [], "bwd": []}
 
-    def step(record):
-        e = [ev() for _ in range(4)] if record else None
+    def step(record=False):
+        e = [ev() for _ in range(5)] if record else None
         if record:
             e[0].record()
-        bvh = R.build_bvh(g, p, workspace=ws)
+        bvh = R.build_bvh(g, base, workspace=ws)
         if record:
             e[1].record()
-        R.render_fwd(bvh, g, rays, p, out=out, state=state)
+        render(bvh, g, pf, out, state)
         if record:
             e[2].record()
         grad = torch.sign(out - target) * (1.0 / (3.0 * nr))  # d/dout of mean L1
         if record:
             e[3].record()
-        R.render_bwd(bvh, g, rays, p, grad, state, grads=grads)
+        adjoint(bvh, pb, grad, state)
         if record:
-            e4 = ev()
-            e4.record()
-            return (e[0], e[1], e[2], e[3], e4)
-        return None
+            e[4].record()
+        return e
 
     def fwd_step():
-        bvh = R.build_bvh(g, p, workspace=ws)
-        R.render_fwd(bvh, g, rays, p, out=out, state=None)
+        bvh = R.build_bvh(g, base, workspace=ws)
+        render(bvh, g, pf, out, None)
 
     if args.profile:
-        step(False)
+        step()
         torch.cuda.synchronize()
-        step(False)
+        step()
         torch.cuda.synchronize()
         src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
         dst = src.clone()  # reads and writes exactly 256 MiB
         torch.cuda.synchronize()
         del src, dst
-        print("[bench] profile step done", file=sys.stderr, flush=True)
+        log("profile step done")
         return
 
     for _ in range(args.warmup):
-        step(False)
+        step()
     torch.cuda.synchronize()
-    status = R.read_status(R.build_bvh(g, p, workspace=ws))
-    torch.cuda.synchronize()
+    status = R.read_status(R.build_bvh(g, base, workspace=ws))
 
-    # timed: forward + backward steps
-    recs = []
-    s0, s1 = ev(), ev()
-    torch.cuda.synchronize()
-    s0.record()
-    for _ in range(args.steps):
-        recs.append(step(True))
-    s1.record()
-    torch.cuda.synchronize()
-    ms_step = s0.elapsed_time(s1) / args.steps
-    for r in recs:
-        kt["build"].append(r[0].elapsed_time(r[1]))
-        kt["fwd"].append(r[1].elapsed_time(r[2]))
-        kt["bwd"].append(r[3].elapsed_time(r[4]))
+    def timed(fn, steps):
+        s0, s1 = ev(), ev()
+        torch.cuda.synchronize()
+        s0.record()
+        res = [fn() for _ in range(steps)]
+        s1.record()
+        torch.cuda.synchronize()
+        return s0.elapsed_time(s1) / steps, res
 
-    # timed: forward-only steps (rebuild + render)
-    f0, f1 = ev(), ev()
-    torch.cuda.synchronize()
-    f0.record()
-    for _ in range(args.steps):
-        fwd_step()
-    f1.record()
-    torch.cuda.synchronize()
-    ms_fwd = f0.elapsed_time(f1) / args.steps
+    # eager steps, with per-phase events
+    ms_eager, recs = timed(lambda: step(True), args.steps)
+    for e in recs:
+        kt["build"].append(e[0].elapsed_time(e[1]))
+        kt["fwd"].append(e[1].elapsed_time(e[2]))
+        kt["bwd"].append(e[3].elapsed_time(e[4]))
+    ms_fwd_eager, _ = timed(fwd_step, args.steps)
+
+    # HIP-graph replays of the same steps
+    ms_graph = ms_fwd_graph = None
+    if not args.no_graph:
+        graphs = []
+        for fn in (step, fwd_step):
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            gph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gph):
+                fn()
+            torch.cuda.synchronize()
+            gph.replay()
+            torch.cuda.synchronize()
+            graphs.append(gph)
+        ms_graph, _ = timed(graphs[0].replay, args.steps)
+        ms_fwd_graph, _ = timed(graphs[1].replay, args.steps)
+        step()  # leave eager results (out, grads) of the current parameters
+        torch.cuda.synchronize()
+    ms_step = ms_graph if ms_graph is not None else ms_eager
+    ms_fwd = ms_fwd_graph if ms_fwd_graph is not None else ms_fwd_eager
 
     med = {k: float(np.median(v)) for k, v in kt.items()}
     mrays_fb = nr / (ms_step * 1e-3) / 1e6
     mrays_f = nr / (ms_fwd * 1e-3) / 1e6
     mrays_render = nr / (med["fwd"] * 1e-3) / 1e6
 
-    # Algorithmic FP32 work of the render kernels, from the library's work counters
-    # (one untimed forward + adjoint with RS_COUNTERS). Per-unit FLOPs are counted from
-    # the kernels' expressions (an FMA is 2, min/max/compare/rcp/sqrt/exp are 1):
-    #   child-box slab test whose box the lane's ray overlaps   22
-    #   ray / ellipsoid test of a live lane at a visited leaf   90
-    #   composited hit (alpha recomputed + Eq. 3 step)          110
-    #   adjoint of a composited hit (dL/dalpha + App. A.6)      265
-    pc = R.Params(kbuf=args.kbuf, flags=flags | 8)
-    bvh_c = R.build_bvh(g, pc, workspace=ws)
-    R.render_fwd(bvh_c, g, rays, pc, out=out, state=state)
+    # ---- batched multi-view launch vs one launch per view (forward and adjoint render only)
+    batching = None
+    if len(views) > 1 and mesh_np is None:
+        bvh = R.build_bvh(g, base, workspace=ws)
+        gr = torch.sign(out - target) * (1.0 / (3.0 * nr))
+        per_rays = [R.Rays(rays.origin[off:off + vw * vh], rays.direction[off:off + vw * vh],
+                           views=[(0, vw, vh)]) for off, vw, vh in views]
+
+        def per_view_fwd():
+            for (off, vw, vh), rr in zip(views, per_rays):
+                R.render_fwd(bvh, g, rr, pf, out=out[off:off + vw * vh], state=state[off:off + vw * vh])
+
+        def per_view_bwd():
+            for (off, vw, vh), rr in zip(views, per_rays):
+                R.render_bwd(bvh, g, rr, pb, gr[off:off + vw * vh], state[off:off + vw * vh], grads=grads)
+
+        per_view_fwd()
+        ms_pv_f, _ = timed(per_view_fwd, args.steps)
+        ms_pv_b, _ = timed(per_view_bwd, args.steps)
+        ms_b_f, _ = timed(lambda: R.render_fwd(bvh, g, rays, pf, out=out, state=state), args.steps)
+        ms_b_b, _ = timed(lambda: R.render_bwd(bvh, g, rays, pb, gr, state, grads=grads), args.steps)
+        batching = dict(batched_fwd_ms=round(ms_b_f, 4), per_view_fwd_ms=round(ms_pv_f, 4),
+                        batched_bwd_ms=round(ms_b_b, 4), per_view_bwd_ms=round(ms_pv_b, 4),
+                        note="per-view: one render launch per view (bwd: per view, accumulating gradients "
+                             "only within its own launch)")
+        step()
+        torch.cuda.synchronize()
+
+    # ---- algorithmic FLOPs from the library's work counters (one untimed forward + adjoint)
+    qf = R.Params(**{**pf.__dict__, "flags": pf.flags | 8})
+    qb = R.Params(**{**pb.__dict__, "flags": pb.flags | 8})
+    bvh_c = R.build_bvh(g, qf, workspace=ws)
+    render(bvh_c, g, qf, out, state)
     cf = R.read_counters(bvh_c)
-    R.render_bwd(bvh_c, g, rays, pc, torch.sign(out - target) * (1.0 / (3.0 * nr)), state, grads=grads)
+    adjoint(bvh_c, qb, torch.sign(out - target) * (1.0 / (3.0 * nr)), state)
     cb = {k: R.read_counters(bvh_c)[k] - cf[k] for k in cf}
-    fwd_flops = 22.0 * cf["lane_child_overlaps"] + 90.0 * cf["lane_leaf_tests"] + 110.0 * cf["lane_composited"]
-    bwd_flops = 22.0 * cb["lane_child_overlaps"] + 90.0 * cb["lane_leaf_tests"] + \
-        (110.0 + 265.0) * cb["lane_composited"]
+    fwd_flops = FLOPS_CHILD * cf["lane_child_overlaps"] + FLOPS_LEAF * cf["lane_leaf_tests"] + \
+        FLOPS_COMPOSITE * cf["lane_composited"]
+    bwd_flops = FLOPS_CHILD * cb["lane_child_overlaps"] + FLOPS_LEAF * cb["lane_leaf_tests"] + \
+        (FLOPS_COMPOSITE + FLOPS_ADJOINT) * cb["lane_composited"]
     dom = "bwd" if med["bwd"] >= med["fwd"] else "fwd"
     dom_flops = bwd_flops if dom == "bwd" else fwd_flops
     achieved = dom_flops / (med[dom] * 1e-3) / 1e12
 
     # HBM traffic per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used
-    # only when they were taken on the current kernel source
+    # only when they were taken on the current kernel source and this workload
     traffic = None
     try:
         import hashlib
@@ -189,35 +285,55 @@ def main():
     except (OSError, KeyError, ValueError):
         traffic = None
 
-    # parity on a seeded sample of pixels against the FP64 oracle
+    # ---- parity on a seeded sample of pixels against the FP64 oracle, and the oracle's own rate
     err = None
     cpu = None
     try:
         from oracle import oracle as O
         f32 = lambda x: float(np.float32(x))
-        op = O.Params(Q=f32(p.Q), eps1=f32(p.eps1), max_hits=p.max_hits)
+        op = O.Params(Q=f32(base.Q), eps1=f32(base.eps1), max_hits=base.max_hits)
         rng = np.random.default_rng(123)
+        out_h = out.cpu().numpy()
+        if mesh_np is not None:
+            from oracle import mesh as OM
+            osh = OM.Shading(light=tuple(float(np.float32(x)) for x in shading.light),
+                             intensity=f32(shading.intensity), albedo=f32(shading.albedo),
+                             mirror_reflectance=f32(shading.mirror_reflectance),
+                             mirror_diffuse=f32(shading.mirror_diffuse), offset=f32(shading.offset))
+            ofwd = lambda s: OM.mesh_forward(sc, mesh_np, osh, o[s], d[s], op)
         if args.parity_rays > 0:
             sel = np.sort(rng.choice(nr, args.parity_rays, replace=False))
-            ref, _, _ = O.render_fwd(sc, o[sel], d[sel], op)
-            res = O.compare_with_alternatives(out.cpu().numpy()[sel], ref, sc, o[sel], d[sel], op, tol=1e-4)
-            err = dict(max_abs_rgb=res["max_err"], within_1e4=res["within"], resolved=res["resolved"],
-                       unresolved=len(res["unresolved"]), sampled=int(args.parity_rays))
+            if mesh_np is not None:
+                ref = ofwd(sel)["rgb"]
+                e_abs = np.abs(out_h[sel] - ref).max(axis=1)
+                err = dict(max_abs_rgb=float(e_abs.max()), within_1e4=int((e_abs <= 1e-4).sum()),
+                           sampled=int(args.parity_rays),
+                           note="mesh path: plain comparison (the full protocol runs in the GPU tests)")
+            else:
+                ref, _, _ = O.render_fwd(sc, o[sel], d[sel], op)
+                res = O.compare_with_alternatives(out_h[sel], ref, sc, o[sel], d[sel], op, tol=1e-4)
+                err = dict(max_abs_rgb=res["max_err"], within_1e4=res["within"], resolved=res["resolved"],
+                           unresolved=len(res["unresolved"]), sampled=int(args.parity_rays))
         if not args.no_cpu_baseline:
             sel = np.sort(rng.choice(nr, args.cpu_rays, replace=False))
-            gsel = (np.sign(out.cpu().numpy()[sel] - target.cpu().numpy()[sel]) / (3.0 * nr)).astype(np.float64)
+            gsel = (np.sign(out_h[sel] - target.cpu().numpy()[sel]) / (3.0 * nr)).astype(np.float64)
             c0 = time.time()
-            O.render_fwd(sc, o[sel], d[sel], op)
-            c1 = time.time()
-            O.render_bwd(sc, o[sel], d[sel], gsel, op)
+            if mesh_np is not None:
+                f = ofwd(sel)
+                c1 = time.time()
+                OM.mesh_backward(sc, mesh_np, osh, o[sel], d[sel], gsel, op, fwd=f)
+            else:
+                O.render_fwd(sc, o[sel], d[sel], op)
+                c1 = time.time()
+                O.render_bwd(sc, o[sel], d[sel], gsel, op)
             c2 = time.time()
             cores = O.lib().orc_max_threads()
             cpu = dict(value=args.cpu_rays / (c2 - c0) / 1e6, unit="Mrays/s", cores=int(cores), kind="oracle",
-                       sample=f"{args.cpu_rays} seeded pixels of the same view, forward + adjoint, brute force "
+                       sample=f"{args.cpu_rays} seeded pixels of the same views, forward + adjoint, brute force "
                               f"over all {n} Gaussians (fwd {c1 - c0:.1f}s, bwd {c2 - c1:.1f}s)",
                        fwd_value=args.cpu_rays / (c1 - c0) / 1e6)
     except Exception as e:  # the oracle is optional on the GPU machine
-        print(f"[bench] oracle leg skipped: {e}", file=sys.stderr)
+        log(f"oracle leg skipped: {e}")
 
     line = {
         "metric": METRIC,
@@ -233,15 +349,24 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
-                   "kbuf": p.kbuf or 24, "persistent": bool(args.persistent), "step": "bvh+fwd+L1+bwd"},
+                   "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
+                   "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None,
+                   "launch_fwd": dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2),
+                                      tile_width=pf.tile_width or 8),
+                   "launch_bwd": dict(kbuf=pb.kbuf or 24, persistent=bool(pb.flags & 2),
+                                      tile_width=pb.tile_width or 8)},
         "fwd_mrays_s": round(mrays_f, 3),
         "render_only_fwd_mrays_s": round(mrays_render, 3),
         "ms_fwd_step": round(ms_fwd, 4),
+        "eager_ms_per_step": round(ms_eager, 4),
+        "eager_ms_fwd_step": round(ms_fwd_eager, 4),
         "kernel_ms_median": {k: round(v, 4) for k, v in med.items()},
         "roofline": {"bound": "alu", "kernel": f"render_{dom}", "achieved": round(achieved, 3), "peak": 157.3,
                      "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": traffic,
                      "algorithmic_flops": float(dom_flops)},
         "work_per_ray": {k: round(v / nr, 2) for k, v in cf.items() if v},
+        "autotune": tune,
+        "batching": batching,
         "device_status": status,
         "parity": err,
         "cpu_baseline": cpu,

@@ -75,7 +75,8 @@ typedef struct {
 
 /* One camera's rays inside the ray array: rays [ray_offset, ray_offset + width*height)
  * are an image of `width` x `height` pixels in row-major order. The renderer
- * groups rays into 8x8 pixel tiles (one wavefront each) for coherence. */
+ * groups rays into 64-pixel tiles (one wavefront each; 8x8 unless
+ * rs_params.tile_width says otherwise) for coherence. */
 typedef struct {
     int64_t ray_offset;
     int32_t width, height;
@@ -99,8 +100,9 @@ typedef struct {
  * threshold (>= 0). t_min: minimum hit depth. max_hits: K_max (0 = unbounded).
  * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 24; the
  * result does not depend on it).
- * stack_depth: traversal stack entries (1..64; 0 = 64). packet_rays: rays per
- * wavefront packet (64; 0 = 64). */
+ * stack_depth: traversal stack entries (1..64; 0 = 64). tile_width: width in
+ * pixels of the 64-ray packet tile of a view (4, 8, 16 or 32, i.e. 4x16, 8x8,
+ * 16x4 or 32x2 pixels; 0 = 8); like kbuf it changes the time, not the result. */
 typedef struct {
     float Q, eps1, t_min;
     int32_t max_hits;
@@ -108,7 +110,7 @@ typedef struct {
     uint32_t flags;
     int32_t kbuf;
     int32_t stack_depth;
-    int32_t packet_rays;
+    int32_t tile_width;
 } rs_params;
 
 /* Gradient outputs (device, float32, same shapes as the inputs). Any pointer
@@ -178,6 +180,31 @@ int rs_read_status(const rs_bvh *bvh, void *stream);
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 
+/* ------------------------------------------------------------- autotuning */
+/* Tuning helper, not part of the method: the launch shape (hit-buffer size
+ * kbuf, plain or persistent grid, packet tile width) changes the time of a
+ * render, never a rendered value (nor a gradient beyond float atomic order). */
+#define RS_TUNE_MAX 32
+typedef struct {
+    rs_params fwd;  /* fastest forward configuration (a copy of *base with the knobs set) */
+    rs_params bwd;  /* fastest adjoint configuration (= fwd when grad_rgb is NULL) */
+    int32_t n;      /* candidates timed */
+    int32_t kbuf[RS_TUNE_MAX], persistent[RS_TUNE_MAX], tile_width[RS_TUNE_MAX];
+    float ms_fwd[RS_TUNE_MAX], ms_bwd[RS_TUNE_MAX]; /* mean ms per launch (bwd 0 without grad_rgb) */
+} rs_tune;
+
+/* Times every candidate on the caller's own BVH, Gaussians and rays: kbuf in
+ * {8, 16, 24, 32} x {one workgroup per packet, persistent queue} x tile width
+ * {8, 16} (8x8 / 16x4 pixels; only 8 when the rays carry no views). Each runs
+ * once untimed, then `reps` (1..100) times between hipEvents on `stream`.
+ * grad_rgb (device [n][3], optional) also times the adjoint, which then
+ * needs ray_state and grads; out_rgb, ray_state and grads receive the
+ * results of the last candidate run. Host-synchronous (waits for `stream`).
+ * Returns the first error of any launch. */
+int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *base,
+                const float *grad_rgb, float *out_rgb, void *ray_state, rs_grads *grads, int reps,
+                rs_tune *result, void *stream);
+
 /* ------------------------------------------------------ mesh + Gaussians */
 /* The paper combines triangle meshes with Gaussians for mirror reflections
  * and shadows (Sec. 1, Figs. 1 and 3-6) without giving a shading model. This
@@ -230,10 +257,10 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
  * their states and the terms the adjoint needs), 256-byte aligned. */
 size_t rs_mesh_frame_bytes(int64_t n_rays);
 
-/* Forward render of Gaussians + mesh with reflection and shadow rays. The
- * reflection and shadow rays of all pixels are traced together in one
- * persistent launch (two ray sets, one packet queue). `frame` must be kept
- * for rs_render_mesh_bwd. */
+/* Forward render of Gaussians + mesh with reflection and shadow rays. After
+ * the triangle traces, the Gaussians along the primary, reflection and shadow
+ * rays of all pixels are rendered in one persistent launch (three ray sets,
+ * one packet queue). `frame` must be kept for rs_render_mesh_bwd. */
 int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
                        const rs_shading *sh, const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame,
                        void *stream);

@@ -29,7 +29,8 @@ RS_MAX_VIEWS = 64
 EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", "rs_build_bvh", "rs_render_fwd",
            "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download",
            "rs_default_shading", "rs_build_mesh_bvh", "rs_trace_mesh", "rs_mesh_frame_bytes", "rs_render_mesh_fwd",
-           "rs_render_mesh_bwd")
+           "rs_render_mesh_bwd", "rs_autotune")
+RS_TUNE_MAX = 32
 
 
 class rs_gaussians(C.Structure):
@@ -49,7 +50,7 @@ class rs_rays(C.Structure):
 class rs_params(C.Structure):
     _fields_ = [("Q", C.c_float), ("eps1", C.c_float), ("t_min", C.c_float), ("max_hits", C.c_int32),
                 ("bg", C.c_float * 3), ("flags", C.c_uint32), ("kbuf", C.c_int32), ("stack_depth", C.c_int32),
-                ("packet_rays", C.c_int32)]
+                ("tile_width", C.c_int32)]
 
 
 class rs_grads(C.Structure):
@@ -69,6 +70,12 @@ class rs_mesh(C.Structure):
 class rs_shading(C.Structure):
     _fields_ = [("light", C.c_float * 3), ("intensity", C.c_float), ("albedo", C.c_float),
                 ("mirror_reflectance", C.c_float), ("mirror_diffuse", C.c_float), ("offset", C.c_float)]
+
+
+class rs_tune(C.Structure):
+    _fields_ = [("fwd", rs_params), ("bwd", rs_params), ("n", C.c_int32), ("kbuf", C.c_int32 * RS_TUNE_MAX),
+                ("persistent", C.c_int32 * RS_TUNE_MAX), ("tile_width", C.c_int32 * RS_TUNE_MAX),
+                ("ms_fwd", C.c_float * RS_TUNE_MAX), ("ms_bwd", C.c_float * RS_TUNE_MAX)]
 
 
 class RaySplatsError(RuntimeError):
@@ -125,6 +132,9 @@ def lib():
                                      C.POINTER(rs_shading), C.POINTER(rs_rays), C.POINTER(rs_params), P, P,
                                      C.POINTER(rs_grads), P]
     L.rs_render_mesh_bwd.restype = C.c_int
+    L.rs_autotune.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_rays), C.POINTER(rs_params), P,
+                              P, P, C.POINTER(rs_grads), C.c_int, C.POINTER(rs_tune), P]
+    L.rs_autotune.restype = C.c_int
     _lib = L
     return L
 

@@ -22,7 +22,8 @@ static int check_params(const rs_params *p)
     if (!(p->Q > 0.0f) || !(p->eps1 >= 0.0f) || p->max_hits < 0 || !(p->t_min == p->t_min)) return RS_ERR_INVALID_ARG;
     if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32) return RS_ERR_INVALID_ARG;
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
-    if (p->packet_rays != 0 && p->packet_rays != 64) return RS_ERR_INVALID_ARG;
+    if (p->tile_width != 0 && p->tile_width != 4 && p->tile_width != 8 && p->tile_width != 16 && p->tile_width != 32)
+        return RS_ERR_INVALID_ARG;
     if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS)) return RS_ERR_INVALID_ARG;
     return RS_OK;
 }
@@ -195,7 +196,8 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
     BvhDesc M;
     if ((e = check_mesh_bvh(mesh_bvh, nullptr, M))) return e;
     if (rays->n > 0 && (!t_hit || !tri)) return RS_ERR_INVALID_ARG;
-    return launch_trace_mesh(M, rays, t_limit, any_hit ? 1 : 0, t_hit, tri, static_cast<hipStream_t>(stream));
+    return launch_trace_mesh(M, rays, t_limit, any_hit ? 1 : 0, tile_shift_of(nullptr), t_hit, tri,
+                             static_cast<hipStream_t>(stream));
 }
 
 size_t rs_mesh_frame_bytes(int64_t n_rays) { return n_rays >= 0 ? mesh_frame_bytes(n_rays) : 0; }
@@ -265,6 +267,78 @@ int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream)
     if (hipMemcpy(&h, D.ws + L.header, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     for (int k = 0; k < 12; ++k) out[k] = h.counters[k];
     return RS_OK;
+}
+
+int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *base,
+                const float *grad_rgb, float *out_rgb, void *ray_state, rs_grads *grads, int reps, rs_tune *result,
+                void *stream)
+{
+    int e = check_gaussians(g);
+    if (e) return e;
+    if ((e = check_params(base))) return e;
+    if ((e = check_rays(rays))) return e;
+    BvhDesc D;
+    if ((e = check_bvh(bvh, g, base, D))) return e;
+    if (!result || reps < 1 || reps > 100) return RS_ERR_INVALID_ARG;
+    if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
+    if (grad_rgb && (!ray_state || !grads)) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    memset(result, 0, sizeof(*result));
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return RS_ERR_HIP;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return RS_ERR_HIP;
+    }
+    // mean ms of `reps` launches of f (after one untimed launch)
+    auto timed = [&](auto &&f, float &ms) -> int {
+        int r = f();
+        if (r) return r;
+        if (hipEventRecord(e0, st) != hipSuccess) return RS_ERR_HIP;
+        for (int k = 0; k < reps; ++k)
+            if ((r = f())) return r;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return RS_ERR_HIP;
+        if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return RS_ERR_HIP;
+        ms /= float(reps);
+        return RS_OK;
+    };
+    static const int kbufs[4] = {8, 16, 24, 32};
+    const int n_tiles = rays->n_views > 0 ? 2 : 1;
+    int best_f = -1, best_b = -1;
+    for (int ki = 0; ki < 4 && !e; ++ki) {
+        for (int pers = 0; pers < 2 && !e; ++pers) {
+            for (int ti = 0; ti < n_tiles && !e; ++ti) {
+                const int c = result->n;
+                rs_params p = *base;
+                p.kbuf = kbufs[ki];
+                p.flags = (base->flags & ~(RS_PERSISTENT | RS_COUNTERS)) | (pers ? RS_PERSISTENT : 0u);
+                p.tile_width = ti == 0 ? 8 : 16;
+                result->kbuf[c] = p.kbuf;
+                result->persistent[c] = pers;
+                result->tile_width[c] = p.tile_width;
+                e = timed([&] { return launch_render(D, g, rays, &p, out_rgb, ray_state, nullptr, nullptr, st); },
+                          result->ms_fwd[c]);
+                if (!e && grad_rgb)
+                    e = timed([&] { return launch_render(D, g, rays, &p, nullptr, ray_state, grad_rgb, grads, st); },
+                              result->ms_bwd[c]);
+                if (e) break;
+                if (best_f < 0 || result->ms_fwd[c] < result->ms_fwd[best_f]) {
+                    best_f = c;
+                    result->fwd = p;
+                }
+                if (grad_rgb && (best_b < 0 || result->ms_bwd[c] < result->ms_bwd[best_b])) {
+                    best_b = c;
+                    result->bwd = p;
+                }
+                result->n = c + 1;
+            }
+        }
+    }
+    if (!grad_rgb) result->bwd = result->fwd;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return e;
 }
 
 const char *rs_status_string(int code)

@@ -1,5 +1,5 @@
 // Device helpers shared by the Gaussian and triangle traversals: packets of
-// 8x8-pixel tiles, rays and conservative slab tests.
+// 64-pixel tiles (8x8 by default), rays and conservative slab tests.
 #pragma once
 
 #include "rs_internal.h"
@@ -20,7 +20,30 @@ constexpr float kInf = __builtin_huge_valf();
 
 // --------------------------------------------------------------- packets
 
-// Packet index -> ray index of this lane (8x8 tiles within each view).
+// Host: fill the view table of a launch (tiles of 2^tile_shift x 64 / 2^tile_shift
+// pixels) and return its packet count.
+template <typename PT>
+inline int64_t plan_packets(PT &P, const rs_rays *rays, int tile_shift)
+{
+    P.n_views = rays->n_views;
+    P.tile_shift = tile_shift;
+    if (rays->n_views == 0) return (rays->n + kWave - 1) / kWave;
+    const int tw = 1 << tile_shift, th = kWave >> tile_shift;
+    int64_t packets = 0;
+    for (int v = 0; v < rays->n_views; ++v) {
+        const rs_view &V = rays->views[v];
+        ViewEntry &E = P.views[v];
+        E.ray_offset = V.ray_offset;
+        E.width = V.width;
+        E.height = V.height;
+        E.tiles_x = (V.width + tw - 1) / tw;
+        E.first_packet = packets;
+        packets += int64_t(E.tiles_x) * ((V.height + th - 1) / th);
+    }
+    return packets;
+}
+
+// Packet index -> ray index of this lane (row-major tiles within each view).
 template <typename PT>
 __device__ inline int64_t packet_ray(const PT &P, int64_t pkt, int lane, bool &valid)
 {
@@ -33,10 +56,11 @@ __device__ inline int64_t packet_ray(const PT &P, int64_t pkt, int lane, bool &v
     for (int k = 1; k < P.n_views; ++k)
         if (pkt >= P.views[k].first_packet) v = k;
     const ViewEntry &V = P.views[v];
+    const int sh = P.tile_shift;
     int64_t local = pkt - V.first_packet;
     int64_t ty = local / V.tiles_x, tx = local - ty * V.tiles_x;
-    int64_t x = tx * kTile + (lane & (kTile - 1));
-    int64_t y = ty * kTile + (lane / kTile);
+    int64_t x = (tx << sh) + (lane & ((1 << sh) - 1));
+    int64_t y = ty * (kWave >> sh) + (lane >> sh);
     valid = x < V.width && y < V.height;
     return V.ray_offset + y * V.width + x;
 }

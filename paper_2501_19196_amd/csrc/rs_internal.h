@@ -11,7 +11,18 @@ namespace rs {
 
 constexpr uint64_t kMagic = 0x5253425648495031ull;  // "RSBVHIP1"
 constexpr int kWave = 64;
-constexpr int kTile = 8;  // 8x8 pixel tiles, one wavefront each
+constexpr int kMaxSets = 3;  // ray sets one render launch can carry
+
+// log2 of the packet tile width of a launch (tile_width 0 = 8x8 tiles)
+inline int tile_shift_of(const rs_params *p)
+{
+    switch (p ? p->tile_width : 0) {
+    case 4: return 2;
+    case 16: return 4;
+    case 32: return 5;
+    default: return 3;
+    }
+}
 constexpr int kSortBlock = 256;
 constexpr int kSortItems = 8;  // keys per thread per sort tile
 constexpr int kSortTile = kSortBlock * kSortItems;
@@ -138,7 +149,7 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
                   void *state, const float *grad, const rs_grads *grads, hipStream_t st);
 void zero_gacc(const BvhDesc &D, hipStream_t st);
 int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st);
-int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
+int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, int tile_shift, float *t_hit,
                       int32_t *tri, hipStream_t st);
 size_t mesh_frame_bytes(int64_t n);
 int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,

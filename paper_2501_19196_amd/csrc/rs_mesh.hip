@@ -18,7 +18,7 @@ struct MeshParams {
     int32_t root;
     int32_t any_hit;
     int32_t n_views;
-    int32_t pad;
+    int32_t tile_shift;
     ViewEntry views[RS_MAX_VIEWS];
 };
 
@@ -45,7 +45,7 @@ __device__ inline float tri_hit(const Ray &ray, const float4 r0, const float4 r1
     return t > 0.0f ? t : kInf;
 }
 
-// One wavefront per 8x8 ray tile, wave-uniform BVH walk (as the Gaussian
+// One wavefront per 64-ray tile, wave-uniform BVH walk (as the Gaussian
 // traversal); each lane keeps its closest hit below its limit. With any_hit a
 // lane stops at its first hit.
 __global__ __launch_bounds__(64) void k_mesh_trace(const float4 *__restrict__ records, const float4 *__restrict__ nodes,
@@ -345,39 +345,23 @@ __global__ void k_mesh_bwd_prep(const Frame F, int64_t n, const float *__restric
 
 static inline int grid_for(int64_t n) { return int((n + 255) / 256); }
 
-static MeshParams mesh_params(const BvhDesc &M, const rs_rays *rays, int any_hit)
+static MeshParams mesh_params(const BvhDesc &M, const rs_rays *rays, int any_hit, int tile_shift)
 {
     MeshParams P{};
     P.n_rays = rays->n;
     P.root = M.root;
     P.n_tris = M.n;
     P.any_hit = any_hit;
-    P.n_views = rays->n_views;
-    int64_t packets = 0;
-    if (rays->n_views == 0) {
-        packets = (rays->n + kWave - 1) / kWave;
-    } else {
-        for (int v = 0; v < rays->n_views; ++v) {
-            const rs_view &V = rays->views[v];
-            ViewEntry &E = P.views[v];
-            E.ray_offset = V.ray_offset;
-            E.width = V.width;
-            E.height = V.height;
-            E.tiles_x = (V.width + kTile - 1) / kTile;
-            E.first_packet = packets;
-            packets += int64_t(E.tiles_x) * ((V.height + kTile - 1) / kTile);
-        }
-    }
-    P.n_packets = packets;
+    P.n_packets = plan_packets(P, rays, tile_shift);
     return P;
 }
 
-int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
-                      int32_t *tri, hipStream_t st)
+int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, int tile_shift,
+                      float *t_hit, int32_t *tri, hipStream_t st)
 {
     Layout L = make_layout(M.n);
     WsHeader *h = reinterpret_cast<WsHeader *>(M.ws + L.header);
-    MeshParams P = mesh_params(M, rays, any_hit);
+    MeshParams P = mesh_params(M, rays, any_hit, tile_shift);
     if (rays->n == 0) return RS_OK;
     k_mesh_trace<<<int(P.n_packets > 0 ? P.n_packets : 1), kWave, 0, st>>>(
         reinterpret_cast<const float4 *>(M.ws + L.records), reinterpret_cast<const float4 *>(M.ws + L.nodes),
@@ -413,6 +397,36 @@ static rs_rays frame_rays(const rs_rays *prim, const float *o, const float *d, c
     return r;
 }
 
+// The three ray sets of a pixel: the primary ray (Gaussians in front of the
+// mesh), its mirror reflection and its shadow ray. Spawning depends only on
+// the triangle traces, so all three render in one persistent launch.
+static void mesh_sets(const Frame &F, const rs_rays *rays, rs_rays sets_rays[3], SetDesc S[3], bool bwd,
+                      const float *grad)
+{
+    sets_rays[0] = frame_rays(rays, rays->origin, rays->dir, F.tmax_p, bwd ? F.shade : F.bg_p);
+    sets_rays[1] = frame_rays(rays, F.r_o, F.r_d, F.r_tmax, F.r_bg);
+    sets_rays[2] = frame_rays(rays, F.s_o, F.s_d, F.s_tmax, nullptr);
+    for (int k = 0; k < 3; ++k) {
+        S[k] = SetDesc{};
+        S[k].rays = &sets_rays[k];
+    }
+    if (bwd) {
+        S[0].state = F.st_pb;  // final colour of the pixel, with the shade as background
+        S[0].grad = grad;
+        S[1].grad = F.g_r;
+        S[2].grad = F.g_s;
+    } else {
+        S[0].out_rgb = F.out_p;
+        S[1].out_rgb = F.out_r;
+        S[2].out_rgb = F.out_s;
+        S[0].state = F.st_p;
+    }
+    S[1].state = F.st_r;
+    S[2].state = F.st_s;
+    S[2].bg[0] = S[2].bg[1] = S[2].bg[2] = 1.0f;  // transmittance: zero colours, white background
+    S[2].zero_colour = 1;
+}
+
 int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,
                     const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame, hipStream_t st)
 {
@@ -421,40 +435,27 @@ int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, c
     Frame F = frame_layout(static_cast<char *>(frame), n);
     const ShadeConst C = shade_const(sh, p);
     Layout LM = make_layout(M.n);
+    const int ts = tile_shift_of(p);
     int e;
-    // 1. primary rays against the mesh, then the Gaussians in front of it
-    if ((e = launch_trace_mesh(M, rays, nullptr, 0, F.t_mesh, F.tri, st))) return e;
+    // 1. triangle traces: primary closest hits, then the secondary rays they spawn
+    if ((e = launch_trace_mesh(M, rays, nullptr, 0, ts, F.t_mesh, F.tri, st))) return e;
     k_mesh_primary_prep<<<grid_for(n), 256, 0, st>>>(F, n, C);
-    rs_rays prim = frame_rays(rays, rays->origin, rays->dir, F.tmax_p, F.bg_p);
-    SetDesc S0{};
-    S0.rays = &prim;
-    S0.out_rgb = F.out_p;
-    S0.state = F.st_p;
-    if ((e = launch_sets(G, g, p, 1, &S0, false, st))) return e;
-    // 2. secondary rays: spawn, bound reflections by the mesh, drop blocked shadow rays
     k_mesh_spawn<<<grid_for(n), 256, 0, st>>>(rays->origin, rays->dir,
                                                reinterpret_cast<const float4 *>(M.ws + LM.records),
                                                reinterpret_cast<const int32_t *>(M.ws + LM.inv), F, n, C);
-    rs_rays refl = frame_rays(rays, F.r_o, F.r_d, F.r_tmax, F.r_bg);
-    rs_rays shad = frame_rays(rays, F.s_o, F.s_d, F.s_tmax, nullptr);
-    if ((e = launch_trace_mesh(M, &refl, F.r_tmax, 0, F.t2, F.tri2, st))) return e;
-    // shadow blockers: any triangle strictly before the light (t_hit reuses out_s as scratch)
-    if ((e = launch_trace_mesh(M, &shad, F.s_tmax, 1, F.out_s, reinterpret_cast<int32_t *>(F.g_s), st))) return e;
+    rs_rays rr[3];
+    SetDesc S[3];
+    mesh_sets(F, rays, rr, S, false, nullptr);
+    if ((e = launch_trace_mesh(M, &rr[1], F.r_tmax, 0, ts, F.t2, F.tri2, st))) return e;
+    // shadow blockers: any triangle strictly before the light (results parked in out_s / g_s)
+    if ((e = launch_trace_mesh(M, &rr[2], F.s_tmax, 1, ts, F.out_s, reinterpret_cast<int32_t *>(F.g_s), st)))
+        return e;
     k_mesh_secondary_prep<<<grid_for(n), 256, 0, st>>>(F, n, C, F.out_s, reinterpret_cast<const int32_t *>(F.g_s));
-    // 3. reflection and shadow rays of all pixels in one persistent launch (two ray sets)
-    SetDesc S2[2]{};
-    S2[0].rays = &refl;
-    S2[0].out_rgb = F.out_r;
-    S2[0].state = F.st_r;
-    S2[1].rays = &shad;
-    S2[1].out_rgb = F.out_s;
-    S2[1].state = F.st_s;
-    S2[1].bg[0] = S2[1].bg[1] = S2[1].bg[2] = 1.0f;
-    S2[1].zero_colour = 1;
+    // 2. Gaussians along all three ray sets in one persistent launch
     rs_params ps = *p;
     ps.flags |= RS_PERSISTENT;
-    if ((e = launch_sets(G, g, &ps, 2, S2, false, st))) return e;
-    // 4. combine
+    if ((e = launch_sets(G, g, &ps, 3, S, false, st))) return e;
+    // 3. combine
     k_mesh_combine<<<grid_for(n), 256, 0, st>>>(F, n, C, out_rgb);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
@@ -467,28 +468,13 @@ int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays
     if (n > 0) {
         Frame F = frame_layout(static_cast<char *>(frame), n);
         k_mesh_bwd_prep<<<grid_for(n), 256, 0, st>>>(F, n, grad);
-        int e;
-        // primary: the shade term is the background of a ray that hit the mesh
-        rs_rays prim = frame_rays(rays, rays->origin, rays->dir, F.tmax_p, F.shade);
-        SetDesc S0{};
-        S0.rays = &prim;
-        S0.state = F.st_pb;
-        S0.grad = grad;
-        if ((e = launch_sets(G, g, p, 1, &S0, true, st))) return e;
-        rs_rays refl = frame_rays(rays, F.r_o, F.r_d, F.r_tmax, F.r_bg);
-        rs_rays shad = frame_rays(rays, F.s_o, F.s_d, F.s_tmax, nullptr);
-        SetDesc S2[2]{};
-        S2[0].rays = &refl;
-        S2[0].state = F.st_r;
-        S2[0].grad = F.g_r;
-        S2[1].rays = &shad;
-        S2[1].state = F.st_s;
-        S2[1].grad = F.g_s;
-        S2[1].bg[0] = S2[1].bg[1] = S2[1].bg[2] = 1.0f;
-        S2[1].zero_colour = 1;
+        rs_rays rr[3];
+        SetDesc S[3];
+        mesh_sets(F, rays, rr, S, true, grad);
         rs_params ps = *p;
         ps.flags |= RS_PERSISTENT;
-        if ((e = launch_sets(G, g, &ps, 2, S2, true, st))) return e;
+        int e;
+        if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
     }
     scatter_gacc(G, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;

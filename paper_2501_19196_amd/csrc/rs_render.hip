@@ -42,6 +42,8 @@ struct RenderParams {
     int32_t brute;
     int32_t count;
     int32_t n_views;
+    int32_t tile_shift;
+    int32_t pad;
     ViewEntry views[RS_MAX_VIEWS];
 };
 
@@ -282,7 +284,7 @@ struct RaySet {
 
 struct Ptrs {
     const float *quat, *rgb;
-    RaySet set[2];
+    RaySet set[kMaxSets];
     int32_t *status;
     uint32_t *queue;
     unsigned long long *counters;
@@ -328,7 +330,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         ++c_pkt;
 
         // the packet's ray set (uniform) and its packet index within the set
-        const int si = pkt >= P.packets_per_set ? 1 : 0;
+        const int si = (pkt >= P.packets_per_set ? 1 : 0) + (pkt >= 2 * P.packets_per_set ? 1 : 0);
         const RaySet &S = ptr.set[si];
         const bool zc = S.zero_colour != 0;
         bool valid;
@@ -670,29 +672,14 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     P.persistent = (p->flags & RS_PERSISTENT) ? 1 : 0;
     P.brute = (p->flags & RS_BRUTE_FORCE) ? 1 : 0;
     P.count = (p->flags & RS_COUNTERS) ? 1 : 0;
-    P.n_views = rays->n_views;
-    int64_t packets = 0;
-    if (rays->n_views == 0) {
-        packets = (rays->n + kWave - 1) / kWave;
-    } else {
-        for (int v = 0; v < rays->n_views; ++v) {
-            const rs_view &V = rays->views[v];
-            ViewEntry &E = P.views[v];
-            E.ray_offset = V.ray_offset;
-            E.width = V.width;
-            E.height = V.height;
-            E.tiles_x = (V.width + kTile - 1) / kTile;
-            E.first_packet = packets;
-            packets += int64_t(E.tiles_x) * ((V.height + kTile - 1) / kTile);
-        }
-    }
+    const int64_t packets = plan_packets(P, rays, tile_shift_of(p));
     P.packets_per_set = packets;
     P.n_packets = packets * nsets;
 
     Ptrs ptr{};
     ptr.quat = g->quat;
     ptr.rgb = g->rgb;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < kMaxSets; ++k) {
         const SetDesc &E = sets[k < nsets ? k : 0];
         RaySet &R = ptr.set[k];
         R.origin = E.rays->origin;

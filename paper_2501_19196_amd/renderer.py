@@ -25,6 +25,7 @@ class Params:
     flags: int = 0
     kbuf: int = 0
     stack_depth: int = 0
+    tile_width: int = 0
 
     def c(self):
         p = L.rs_params()
@@ -34,7 +35,7 @@ class Params:
         p.flags = int(self.flags)
         p.kbuf = int(self.kbuf)
         p.stack_depth = int(self.stack_depth)
-        p.packet_rays = 0
+        p.tile_width = int(self.tile_width)
         return p
 
 
@@ -157,6 +158,36 @@ def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, sta
     L.check(lib.rs_render_bwd(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(grad_rgb),
                               _ptr(state), C.byref(gr), _stream()), "rs_render_bwd")
     return grads
+
+
+def _params_from_c(cp, like):
+    return Params(Q=like.Q, eps1=like.eps1, t_min=like.t_min, max_hits=like.max_hits, bg=tuple(like.bg),
+                  flags=int(cp.flags), kbuf=int(cp.kbuf), stack_depth=int(cp.stack_depth),
+                  tile_width=int(cp.tile_width))
+
+
+def autotune(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb=None, reps=2):
+    """Time the launch shapes (rs_autotune) on these inputs. Returns
+    (fastest forward Params, fastest adjoint Params, rows of timings)."""
+    n = rays.n
+    dev = rays.origin.device
+    out = torch.empty((n, 3), dtype=torch.float32, device=dev)
+    state = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    gr = None
+    keep = None
+    if grad_rgb is not None:
+        grad_rgb = _dev(grad_rgb.contiguous(), "grad_rgb")
+        keep = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
+                torch.empty_like(g.opacity), torch.empty_like(g.rgb))
+        gr = L.rs_grads(*[_ptr(t) for t in keep])
+    res = L.rs_tune()
+    gc, rc, pc = g.c(), rays.c(), params.c()
+    L.check(L.lib().rs_autotune(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(grad_rgb), _ptr(out),
+                                _ptr(state), C.byref(gr) if gr is not None else None, int(reps), C.byref(res),
+                                _stream()), "rs_autotune")
+    rows = [dict(kbuf=res.kbuf[k], persistent=bool(res.persistent[k]), tile_width=res.tile_width[k],
+                 ms_fwd=float(res.ms_fwd[k]), ms_bwd=float(res.ms_bwd[k])) for k in range(res.n)]
+    return _params_from_c(res.fwd, params), _params_from_c(res.bwd, params), rows
 
 
 def read_status(bvh: BVH):

@@ -32,12 +32,34 @@ def test_library_exports_every_declared_symbol(L):
     assert sorted(L.EXPORTS) == declared
 
 
-def test_struct_sizes_match_header(L):
-    # rs_rays: int64, 4 pointers, int32 (+pad), pointer
-    assert C.sizeof(L.rs_rays) == 8 + 4 * 8 + 8 + 8
-    assert C.sizeof(L.rs_params) == 4 * 4 + 12 + 4 * 4
-    assert C.sizeof(L.rs_bvh) == 128
-    assert C.sizeof(L.rs_gaussians) == 8 + 5 * 8
+def test_struct_layouts_match_header(L, tmp_path):
+    """Every ctypes struct of the binding has the C compiler's size and field
+    offsets for the header's struct (a small C program reads them)."""
+    structs = [L.rs_gaussians, L.rs_view, L.rs_rays, L.rs_params, L.rs_grads, L.rs_bvh, L.rs_mesh, L.rs_shading,
+               L.rs_tune]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "raysplats.h"', "int main(void) {"]
+    for st in structs:
+        name = st.__name__
+        lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
+        for f in st._fields_:
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    import subprocess
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, v = line.split()
+            got[(a, b)] = int(v)
+    for st in structs:
+        name = st.__name__
+        assert got[(name, "size")] == C.sizeof(st), name
+        for f in st._fields_:
+            assert got[(name, f[0])] == getattr(st, f[0]).offset, (name, f[0])
 
 
 def test_defaults_and_strings(L):
