@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--kbuf", type=int, default=0, help="fixed hit-buffer size (implies --no-autotune)")
     ap.add_argument("--persistent", action="store_true", help="persistent grid (implies --no-autotune)")
     ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
+    ap.add_argument("--hit-list", type=int, default=512,
+                    help="stored hit-list capacity per ray (0 = the adjoint re-traverses the BVH)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -88,7 +90,9 @@ def main():
     g = R.Gaussians(*(t(a) for a in sc.arrays()))
     rays = R.Rays(t(o), t(d), views=views)
     fixed = args.kbuf or args.persistent or args.tile_width
-    base = R.Params(kbuf=args.kbuf, flags=2 if args.persistent else 0, tile_width=args.tile_width)
+    # the mesh renders always recompute (their three ray sets keep no lists)
+    base = R.Params(kbuf=args.kbuf, flags=2 if args.persistent else 0, tile_width=args.tile_width,
+                    hit_list=args.hit_list if mesh_np is None else 0)
     nr = o.shape[0]
     n = sc.n
 
@@ -122,7 +126,7 @@ def main():
 
     ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device=dev)
     out = torch.empty((nr, 3), dtype=torch.float32, device=dev)
-    state = torch.empty((nr, 4), dtype=torch.float32, device=dev)
+    state = R.new_state(nr, base, dev)  # colour + T, and the stored hit lists
     grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
              torch.empty_like(g.opacity), torch.empty_like(g.rgb))
     ev = lambda: torch.cuda.Event(enable_timing=True)
@@ -232,8 +236,12 @@ def main():
     # ---- batched multi-view launch vs one launch per view (forward and adjoint render only)
     batching = None
     if len(views) > 1 and mesh_np is None:
+        import dataclasses
         bvh = R.build_bvh(g, base, workspace=ws)
         gr = torch.sign(out - target) * (1.0 / (3.0 * nr))
+        # per-view slices of the ray state need the plain layout: this comparison recomputes
+        pf, pb = dataclasses.replace(pf, hit_list=0), dataclasses.replace(pb, hit_list=0)
+        state = torch.empty((nr, 4), dtype=torch.float32, device=dev)
         per_rays = [R.Rays(rays.origin[off:off + vw * vh], rays.direction[off:off + vw * vh],
                            views=[(0, vw, vh)]) for off, vw, vh in views]
 
@@ -254,6 +262,8 @@ def main():
                         batched_bwd_ms=round(ms_b_b, 4), per_view_bwd_ms=round(ms_pv_b, 4),
                         note="per-view: one render launch per view (bwd: per view, accumulating gradients "
                              "only within its own launch)")
+        pf, pb = dataclasses.replace(pf, hit_list=base.hit_list), dataclasses.replace(pb, hit_list=base.hit_list)
+        state = R.new_state(nr, base, dev)
         step()
         torch.cuda.synchronize()
 
@@ -267,8 +277,9 @@ def main():
     cb = {k: R.read_counters(bvh_c)[k] - cf[k] for k in cf}
     fwd_flops = FLOPS_CHILD * cf["lane_child_overlaps"] + FLOPS_LEAF * cf["lane_leaf_tests"] + \
         FLOPS_COMPOSITE * cf["lane_composited"]
+    # the adjoint replays composited hits from the stored lists (r10) or by re-traversal
     bwd_flops = FLOPS_CHILD * cb["lane_child_overlaps"] + FLOPS_LEAF * cb["lane_leaf_tests"] + \
-        (FLOPS_COMPOSITE + FLOPS_ADJOINT) * cb["lane_composited"]
+        (FLOPS_COMPOSITE + FLOPS_ADJOINT) * (cb["lane_composited"] + cb["r10"])
     dom = "bwd" if med["bwd"] >= med["fwd"] else "fwd"
     dom_flops = bwd_flops if dom == "bwd" else fwd_flops
     achieved = dom_flops / (med[dom] * 1e-3) / 1e12
@@ -350,7 +361,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
                    "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
-                   "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None,
+                   "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None, "hit_list": base.hit_list,
                    "launch_fwd": dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2),
                                       tile_width=pf.tile_width or 8),
                    "launch_bwd": dict(kbuf=pb.kbuf or 24, persistent=bool(pb.flags & 2),

@@ -61,7 +61,8 @@ enum {
 #define RS_PERSISTENT   (1u << 1)  /* persistent launch: waves pop ray packets from a queue */
 #define RS_ZERO_COLOUR  (1u << 2)  /* take every Gaussian colour as 0: output = T * background
                                       (transmittance / shadow rays) */
-#define RS_COUNTERS     (1u << 3)  /* count traversal work (see rs_read_counters); small overhead */
+#define RS_COUNTERS     (1u << 3)  /* count traversal work (see rs_read_counters; not with
+                                      RS_BRUTE_FORCE); an instrumented kernel variant */
 
 #define RS_MAX_VIEWS 64
 
@@ -97,12 +98,18 @@ typedef struct {
 } rs_rays;
 
 /* Renderer knobs. Q: ellipsoid quantile (Sec. 3; > 0). eps1: transmittance
- * threshold (>= 0). t_min: minimum hit depth. max_hits: K_max (0 = unbounded).
+ * threshold (>= 0). t_min: minimum hit depth (finite, >= 0). max_hits: K_max (0 = unbounded).
  * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 24; the
  * result does not depend on it).
  * stack_depth: traversal stack entries (1..64; 0 = 64). tile_width: width in
  * pixels of the 64-ray packet tile of a view (4, 8, 16 or 32, i.e. 4x16, 8x8,
- * 16x4 or 32x2 pixels; 0 = 8); like kbuf it changes the time, not the result. */
+ * 16x4 or 32x2 pixels; 0 = 8); like kbuf it changes the time, not the result.
+ * hit_list: store-or-recompute choice of the adjoint (0..4096; 0 = recompute):
+ * with C > 0 the forward also records, per ray, the ids of the first C
+ * Gaussians it composites (4 C bytes per ray of ray state) and the adjoint
+ * replays those lists instead of traversing the BVH again; rays that
+ * composite more than C hits are re-traversed. The gradients are the same
+ * (up to float atomic order). Ignored by the mesh renders. */
 typedef struct {
     float Q, eps1, t_min;
     int32_t max_hits;
@@ -111,6 +118,7 @@ typedef struct {
     int32_t kbuf;
     int32_t stack_depth;
     int32_t tile_width;
+    int32_t hit_list;
 } rs_params;
 
 /* Gradient outputs (device, float32, same shapes as the inputs). Any pointer
@@ -132,9 +140,10 @@ void rs_default_params(rs_params *p);
 /* Device workspace needed to build and keep a BVH over n Gaussians. */
 size_t rs_bvh_workspace_bytes(int64_t n_gaussians);
 
-/* Per-ray state written by rs_render_fwd and read by rs_render_bwd
- * (16 bytes per ray: composited colour and final transmittance). */
-size_t rs_ray_state_bytes(int64_t n_rays);
+/* Per-ray state written by rs_render_fwd and read by rs_render_bwd: 16 bytes
+ * per ray (composited colour, final transmittance) and, when p->hit_list = C
+ * > 0, a hit count and C Gaussian ids per ray (p may be NULL: C = 0). */
+size_t rs_ray_state_bytes(int64_t n_rays, const rs_params *p);
 
 /* Build the BVH (linear BVH over 30-bit Morton codes of the means, LDS radix
  * sort, Karras radix-tree linking, bottom-up box refit). The paper traverses
@@ -152,17 +161,18 @@ int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_
 /* Forward render (Sec. 3 "Color Aggregation", Eq. 3, Props. 1-2).
  *  bvh        from rs_build_bvh over the same scene size and Q
  *  out_rgb    device float32 [rays->n][3], written
- *  ray_state  device buffer of rs_ray_state_bytes(rays->n) bytes, 16-byte
- *             aligned, written; needed by rs_render_bwd (may be NULL when no
- *             backward pass follows) */
+ *  ray_state  device buffer of rs_ray_state_bytes(rays->n, p) bytes, 16-byte
+ *             aligned (256-byte with p->hit_list > 0), written; needed by
+ *             rs_render_bwd (may be NULL when no backward pass follows) */
 int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
                   float *out_rgb, void *ray_state, void *stream);
 
-/* Adjoint render (App. A.3-A.6): re-traverses every ray, recomputing its
- * hits front to back instead of storing them, and accumulates
- * d/dtheta sum_k <grad_rgb[k], C_k> into `out` with wave-aggregated float32
- * atomics. Must use the same bvh, scene, rays and params as the forward call
- * that wrote ray_state. grad_rgb: device float32 [rays->n][3]. */
+/* Adjoint render (App. A.3-A.6): replays each ray's hits front to back, from
+ * its stored hit list (p->hit_list > 0) or by traversing the BVH again, and
+ * accumulates d/dtheta sum_k <grad_rgb[k], C_k> into `out` with
+ * wave-aggregated float32 atomics. Must use the same bvh, scene, rays and
+ * params (hit_list included) as the forward call that wrote ray_state.
+ * grad_rgb: device float32 [rays->n][3]. */
 int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
                   const float *grad_rgb, const void *ray_state, rs_grads *out, void *stream);
 
@@ -176,7 +186,8 @@ int rs_read_status(const rs_bvh *bvh, void *stream);
  * rounds (all per wavefront), [4] lane leaf tests on live rays, [5] hits
  * entering a lane's buffer, [6] composited hits, [7] lane child-box overlaps,
  * [8] adjoint: per-wave gradient groups (distinct Gaussians per slot),
- * [9]-[11] reserved (0).
+ * stored-list adjoint: [9] ray packets, [10] composited hits, [11] gradient
+ * groups.
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 

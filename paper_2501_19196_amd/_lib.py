@@ -50,7 +50,7 @@ class rs_rays(C.Structure):
 class rs_params(C.Structure):
     _fields_ = [("Q", C.c_float), ("eps1", C.c_float), ("t_min", C.c_float), ("max_hits", C.c_int32),
                 ("bg", C.c_float * 3), ("flags", C.c_uint32), ("kbuf", C.c_int32), ("stack_depth", C.c_int32),
-                ("tile_width", C.c_int32)]
+                ("tile_width", C.c_int32), ("hit_list", C.c_int32)]
 
 
 class rs_grads(C.Structure):
@@ -99,7 +99,7 @@ def lib():
     L.rs_default_params.restype = None
     L.rs_bvh_workspace_bytes.argtypes = [C.c_int64]
     L.rs_bvh_workspace_bytes.restype = C.c_size_t
-    L.rs_ray_state_bytes.argtypes = [C.c_int64]
+    L.rs_ray_state_bytes.argtypes = [C.c_int64, C.POINTER(rs_params)]
     L.rs_ray_state_bytes.restype = C.c_size_t
     L.rs_build_bvh.argtypes = [C.POINTER(rs_gaussians), C.POINTER(rs_params), P, C.c_size_t, C.POINTER(rs_bvh), P]
     L.rs_build_bvh.restype = C.c_int

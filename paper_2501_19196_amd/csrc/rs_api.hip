@@ -19,12 +19,14 @@ static int check_gaussians(const rs_gaussians *g)
 static int check_params(const rs_params *p)
 {
     if (!p) return RS_ERR_INVALID_ARG;
-    if (!(p->Q > 0.0f) || !(p->eps1 >= 0.0f) || p->max_hits < 0 || !(p->t_min == p->t_min)) return RS_ERR_INVALID_ARG;
+    if (!(p->Q > 0.0f) || !(p->eps1 >= 0.0f) || p->max_hits < 0 || !(p->t_min >= 0.0f) || !(p->t_min < 3.0e38f))
+        return RS_ERR_INVALID_ARG;
     if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32) return RS_ERR_INVALID_ARG;
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
     if (p->tile_width != 0 && p->tile_width != 4 && p->tile_width != 8 && p->tile_width != 16 && p->tile_width != 32)
         return RS_ERR_INVALID_ARG;
     if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS)) return RS_ERR_INVALID_ARG;
+    if (p->hit_list < 0 || p->hit_list > 4096) return RS_ERR_INVALID_ARG;
     return RS_OK;
 }
 
@@ -74,7 +76,10 @@ size_t rs_bvh_workspace_bytes(int64_t n_gaussians)
     return make_layout(n_gaussians).total;
 }
 
-size_t rs_ray_state_bytes(int64_t n_rays) { return n_rays > 0 ? size_t(n_rays) * 16 : 0; }
+size_t rs_ray_state_bytes(int64_t n_rays, const rs_params *p)
+{
+    return n_rays > 0 ? state_layout(n_rays, p ? p->hit_list : 0).total : 0;
+}
 
 int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_bytes, rs_bvh *out, void *stream)
 {
@@ -108,7 +113,7 @@ int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
     BvhDesc D;
     if ((e = check_bvh(bvh, g, p, D))) return e;
     if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
-    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, p->hit_list > 0 ? 256 : 16)) return RS_ERR_INVALID_ARG;
     return launch_render(D, g, rays, p, out_rgb, ray_state, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
@@ -122,7 +127,8 @@ int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
     BvhDesc D;
     if ((e = check_bvh(bvh, g, p, D))) return e;
     if (!out) return RS_ERR_INVALID_ARG;
-    if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, 16))) return RS_ERR_INVALID_ARG;
+    if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, p->hit_list > 0 ? 256 : 16)))
+        return RS_ERR_INVALID_ARG;
     return launch_render(D, g, rays, p, nullptr, const_cast<void *>(ray_state), grad_rgb, out,
                          static_cast<hipStream_t>(stream));
 }
@@ -282,7 +288,7 @@ int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, c
     if (!result || reps < 1 || reps > 100) return RS_ERR_INVALID_ARG;
     if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
     if (grad_rgb && (!ray_state || !grads)) return RS_ERR_INVALID_ARG;
-    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, base->hit_list > 0 ? 256 : 16)) return RS_ERR_INVALID_ARG;
     memset(result, 0, sizeof(*result));
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;

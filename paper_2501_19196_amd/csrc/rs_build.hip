@@ -202,10 +202,10 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_scatter(const uint32_t *__r
         bool valid = i < n;
         uint32_t key = valid ? kin[i] : 0u, val = valid ? vin[i] : 0u;
         uint32_t digit = (key >> shift) & 255u;
-        uint64_t peers = __ballot(valid);
+        uint64_t peers = wave_ballot(valid);
         for (int bit = 0; bit < 8; ++bit) {
             bool on = (digit >> bit) & 1u;
-            uint64_t bal = __ballot(valid && on);
+            uint64_t bal = wave_ballot(valid && on);
             peers &= on ? bal : ~bal;
         }
         if (!valid) peers = 0;

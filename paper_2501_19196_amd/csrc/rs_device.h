@@ -9,7 +9,7 @@ namespace rs {
 struct ViewEntry {
     int64_t ray_offset;
     int64_t first_packet;
-    int32_t width, height, tiles_x, pad;
+    int32_t width, height, tiles_x, tiles_y;
 };
 
 struct Ray {
@@ -37,10 +37,32 @@ inline int64_t plan_packets(PT &P, const rs_rays *rays, int tile_shift)
         E.width = V.width;
         E.height = V.height;
         E.tiles_x = (V.width + tw - 1) / tw;
+        E.tiles_y = (V.height + th - 1) / th;
         E.first_packet = packets;
-        packets += int64_t(E.tiles_x) * ((V.height + th - 1) / th);
+        packets += int64_t(E.tiles_x) * E.tiles_y;
     }
     return packets;
+}
+
+// Strip-major order of a view's tiles: the view is cut into vertical strips
+// of `strip` tiles and each strip is walked row by row, so that a contiguous
+// range of this order covers a compact image region. Maps an index of that
+// order to the row-major tile index (both counted over all views).
+template <typename PT>
+__device__ inline int64_t strip_major_packet(const PT &P, int64_t pkt, int strip)
+{
+    if (P.n_views == 0 || strip <= 0) return pkt;
+    int v = 0;
+    for (int k = 1; k < P.n_views; ++k)
+        if (pkt >= P.views[k].first_packet) v = k;
+    const ViewEntry &V = P.views[v];
+    const uint32_t l = uint32_t(pkt - V.first_packet);
+    const uint32_t tx_n = uint32_t(V.tiles_x), ty_n = uint32_t(V.tiles_y), sw = uint32_t(strip);
+    const uint32_t s = l / (sw * ty_n);
+    const uint32_t rem = l - s * sw * ty_n;
+    const uint32_t w = tx_n - s * sw < sw ? tx_n - s * sw : sw;
+    const uint32_t ty = rem / w, tx = s * sw + (rem - ty * w);
+    return V.first_packet + int64_t(ty) * tx_n + tx;
 }
 
 // Packet index -> ray index of this lane (row-major tiles within each view).
@@ -77,6 +99,20 @@ struct Slab {
 
 __device__ inline float widen(float t, float pad) { return __builtin_fmaf(fabsf(t), kWiden, t) + pad; }
 
+// A child box's exit distance widened for the overlap test: t (1 + 2^-19) + pad.
+// Equal to widen(t, pad) for t >= 0; for t < 0 (box behind the origin up to
+// rounding) it still exceeds the exact exit distance, since the rounding error
+// of a slab distance near 0 is below 2^-22 |o/d|, less than pad.
+constexpr float kWidenUp = 1.0000019073486328125f;  // 1 + 2^-19
+__device__ inline float widen_exit(float t, float pad) { return __builtin_fmaf(t, kWidenUp, pad); }
+
+// Whether [near, exit] meets [t_lo, t_hi] (written as compares so that no
+// min/max of loop-carried values needs NaN canonicalisation).
+__device__ inline bool overlaps(float near, float exit_w, float t_lo, float t_hi_w)
+{
+    return near <= exit_w && near <= t_hi_w && t_lo <= exit_w;
+}
+
 // Slab constants of a ray (zero direction components replaced by a tiny value of the same sign).
 __device__ inline Slab make_slab(const Ray &ray)
 {
@@ -94,32 +130,30 @@ __device__ inline Slab make_slab(const Ray &ray)
     return sl;
 }
 
-// Direction signs shared by every valid lane of the wave: when they agree per
-// axis (uni), the near and far planes of a box are chosen once per wave.
-struct WaveSigns {
-    bool uni, px, py, pz;
-};
+// Direction octant shared by every valid lane of the wave (bit 0: +x, bit 1:
+// +y, bit 2: +z), or kMixedOctant when the lanes' direction signs differ.
+constexpr int kMixedOctant = 8;
 
-__device__ inline WaveSigns wave_signs(const Slab &sl, bool valid)
+__device__ inline int wave_octant(const Slab &sl, bool valid)
 {
-    const uint64_t vmask = __ballot(valid);
-    const uint64_t bx = __ballot(valid && sl.ix >= 0.0f), by = __ballot(valid && sl.iy >= 0.0f),
-                   bz = __ballot(valid && sl.iz >= 0.0f);
-    WaveSigns w;
-    w.uni = (bx == 0 || bx == vmask) && (by == 0 || by == vmask) && (bz == 0 || bz == vmask);
-    w.px = bx != 0;
-    w.py = by != 0;
-    w.pz = bz != 0;
-    return w;
+    const uint64_t vmask = wave_ballot(valid);
+    const uint64_t bx = wave_ballot(valid && sl.ix >= 0.0f), by = wave_ballot(valid && sl.iy >= 0.0f),
+                   bz = wave_ballot(valid && sl.iz >= 0.0f);
+    const bool uni = (bx == 0 || bx == vmask) && (by == 0 || by == vmask) && (bz == 0 || bz == vmask);
+    const int oct = (bx != 0 ? 1 : 0) | (by != 0 ? 2 : 0) | (bz != 0 ? 4 : 0);
+    return __builtin_amdgcn_readfirstlane(uni ? oct : kMixedOctant);
 }
 
 // Entry and exit distances of both child boxes of a node
-// (L = (n0.xyz, n0.w n1.xy), R = (n1.zw n2.x, n2.yzw)).
-__device__ inline void child_slabs(const float4 n0, const float4 n1, const float4 n2, const Slab &sl,
-                                   const WaveSigns &ws, float &ln, float &lf, float &rn, float &rf)
+// (L = (n0.xyz, n0.w n1.xy), R = (n1.zw n2.x, n2.yzw)). For a known octant the
+// near and far planes are fixed at compile time (12 FMAs and 4 min3/max3);
+// the mixed form orders each plane pair per lane.
+template <int OCT>
+__device__ inline void child_slabs(const float4 n0, const float4 n1, const float4 n2, const Slab &sl, float &ln,
+                                   float &lf, float &rn, float &rf)
 {
-    if (ws.uni) {
-        const bool px = ws.px, py = ws.py, pz = ws.pz;
+    if constexpr (OCT != kMixedOctant) {
+        constexpr bool px = (OCT & 1) != 0, py = (OCT & 2) != 0, pz = (OCT & 4) != 0;
         ln = fmaxf(fmaxf(__builtin_fmaf(px ? n0.x : n0.w, sl.ix, sl.nx), __builtin_fmaf(py ? n0.y : n1.x, sl.iy, sl.ny)),
                    __builtin_fmaf(pz ? n0.z : n1.y, sl.iz, sl.nz));
         lf = fminf(fminf(__builtin_fmaf(px ? n0.w : n0.x, sl.ix, sl.nx), __builtin_fmaf(py ? n1.x : n0.y, sl.iy, sl.ny)),
@@ -141,6 +175,5 @@ __device__ inline void child_slabs(const float4 n0, const float4 n1, const float
         rf = fminf(fminf(fmaxf(rx0, rx1), fmaxf(ry0, ry1)), fmaxf(rz0, rz1));
     }
 }
-
 
 }  // namespace rs

@@ -12,6 +12,8 @@ namespace rs {
 constexpr uint64_t kMagic = 0x5253425648495031ull;  // "RSBVHIP1"
 constexpr int kWave = 64;
 constexpr int kMaxSets = 3;  // ray sets one render launch can carry
+constexpr int kXcdQueues = 8;  // persistent packet queues (one per XCD of MI355X)
+constexpr int kStripTiles = 16;  // persistent packet order: strips 16 tiles wide
 
 // log2 of the packet tile width of a launch (tile_width 0 = 8x8 tiles)
 inline int tile_shift_of(const rs_params *p)
@@ -47,7 +49,8 @@ struct WsHeader {
     uint32_t bounds[6];    // ordered-uint min xyz, max xyz of the means
     float root_box[6];
     uint64_t counters[12];  // instrumentation (RS_COUNTERS)
-    uint32_t pad[26];
+    uint32_t xq[8];         // persistent packet counters, one per XCD chunk
+    uint32_t pad[18];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
@@ -109,6 +112,10 @@ static_assert(sizeof(BvhDesc) <= sizeof(rs_bvh), "descriptor size");
 
 // ---------------------------------------------------------------- helpers
 
+// Wave-wide vote as a plain 64-bit lane mask (no int materialisation of the
+// predicate, unlike the generic ballot).
+__device__ inline uint64_t wave_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
+
 __device__ inline uint32_t float_to_ordered(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -121,30 +128,39 @@ __device__ inline float ordered_to_float(uint32_t u)
     return __uint_as_float(b);
 }
 
-// 64-bit hit key: ordered bits of t1 above the Gaussian index, so that an
-// unsigned compare orders hits by (t1, index).
-__device__ inline uint64_t make_key(float t1, uint32_t gid)
-{
-    return (uint64_t(float_to_ordered(t1)) << 32) | gid;
-}
-
-__device__ inline float key_t(uint64_t k) { return ordered_to_float(uint32_t(k >> 32)); }
-
-constexpr uint64_t kKeyNone = ~0ull;
-
 // Host description of one ray set of a render launch.
 struct SetDesc {
     const rs_rays *rays;
     float *out_rgb;
     void *state;
     const float *grad;
+    int32_t *count;  // stored hit lists (optional)
+    int32_t *ids;
     float bg[3];
     int32_t zero_colour;
 };
 
+// Ray state: float4 (final colour, final T) per ray; with a hit-list capacity
+// C > 0 it continues (256-byte aligned sections) with int32 count[n] and
+// int32 ids[C][n] (the k-th composited Gaussian of ray r at ids[k][r]).
+struct StateLayout {
+    size_t count, ids, total;
+};
+inline StateLayout state_layout(int64_t n, int32_t cap)
+{
+    StateLayout L{0, 0, 0};
+    const size_t nn = size_t(n > 0 ? n : 0);
+    L.total = nn * 16;
+    if (cap <= 0 || nn == 0) return L;
+    L.count = align256(L.total);
+    L.ids = align256(L.count + nn * 4);
+    L.total = L.ids + nn * size_t(cap) * 4;
+    return L;
+}
+
 int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st);
 int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets, bool bwd,
-                hipStream_t st);
+                hipStream_t st, bool list_adjoint = false);
 int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
                   void *state, const float *grad, const rs_grads *grads, hipStream_t st);
 void zero_gacc(const BvhDesc &D, hipStream_t st);

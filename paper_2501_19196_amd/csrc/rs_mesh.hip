@@ -74,7 +74,6 @@ __global__ __launch_bounds__(64) void k_mesh_trace(const float4 *__restrict__ re
         ray.dz = 1.0f;
     }
     const Slab sl = make_slab(ray);
-    const WaveSigns wsg = wave_signs(sl, valid);
     bool live = valid && limit > 0.0f && P.n_tris > 0;
     float best = limit;  // hits need t < best
     int32_t best_tri = -1;
@@ -83,19 +82,19 @@ __global__ __launch_bounds__(64) void k_mesh_trace(const float4 *__restrict__ re
     int32_t node = P.root;
     int32_t sp = 0, stackv = 0;
     bool overflow = false;
-    if (__ballot(live)) {
+    if (wave_ballot(live)) {
         for (;;) {
             while (node >= 0) {
                 const int64_t ns = __builtin_amdgcn_readfirstlane(node);
                 const float4 n0 = nodes[4 * ns], n1 = nodes[4 * ns + 1], n2 = nodes[4 * ns + 2], n3 = nodes[4 * ns + 3];
                 float ln, lf, rn, rf;
-                child_slabs(n0, n1, n2, sl, wsg, ln, lf, rn, rf);
-                const bool hl = live && fmaxf(ln, 0.0f) <= fminf(widen(lf, sl.pad), t_hi_w);
-                const bool hr = live && fmaxf(rn, 0.0f) <= fminf(widen(rf, sl.pad), t_hi_w);
-                const uint64_t bl = __ballot(hl), br = __ballot(hr);
+                child_slabs<kMixedOctant>(n0, n1, n2, sl, ln, lf, rn, rf);
+                const bool hl = live && overlaps(ln, widen_exit(lf, sl.pad), 0.0f, t_hi_w);
+                const bool hr = live && overlaps(rn, widen_exit(rf, sl.pad), 0.0f, t_hi_w);
+                const uint64_t bl = wave_ballot(hl), br = wave_ballot(hr);
                 const int32_t left = __float_as_int(n3.x), right = __float_as_int(n3.y);
                 if (bl && br) {
-                    const uint64_t pref = __ballot(hl && (!hr || ln <= rn));
+                    const uint64_t pref = wave_ballot(hl && (!hr || ln <= rn));
                     const bool lfirst = 2 * __popcll(pref) >= __popcll(bl | br);
                     if (sp >= 64) {
                         overflow = true;
@@ -128,7 +127,7 @@ __global__ __launch_bounds__(64) void k_mesh_trace(const float4 *__restrict__ re
                     if (P.any_hit) live = false;
                 }
             }
-            if (!__ballot(live)) break;
+            if (!wave_ballot(live)) break;
             if (sp == 0) break;
             --sp;
             node = __builtin_amdgcn_readlane(stackv, sp);

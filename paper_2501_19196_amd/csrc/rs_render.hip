@@ -43,7 +43,9 @@ struct RenderParams {
     int32_t count;
     int32_t n_views;
     int32_t tile_shift;
-    int32_t pad;
+    int32_t strip_tiles;   // persistent: tile strip width of the packet order (0 = row-major)
+    int32_t hit_cap;       // stored hit-list capacity per ray (0 = none)
+    int64_t chunk;         // persistent: packets per XCD queue
     ViewEntry views[RS_MAX_VIEWS];
 };
 
@@ -100,14 +102,32 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
 
 // ------------------------------------------------------------- hit buffer
 
+// A hit's sort key (t1, Gaussian index) packed into the bit pattern of a
+// positive normal double: ((float bits of t1) + 2^20) << 32 | index. For
+// t1 >= 0 the double order is the (t1, index) order, so a sorted insert is a
+// chain of v_min_f64 / v_max_f64 (no compares, selects or hazards).
+constexpr uint32_t kKeyBias = 0x00100000u;  // keeps every key a normal double
+constexpr double kNoHit = __builtin_huge_val();  // empty slot, above every key
+
+__device__ inline double hit_key(float t1, uint32_t gid)
+{
+    const uint64_t hi = uint64_t(__float_as_uint(t1) + kKeyBias);
+    return __longlong_as_double((long long)((hi << 32) | gid));
+}
+__device__ inline float hit_key_t(double k)
+{
+    return __uint_as_float(uint32_t(uint64_t(__double_as_longlong(k)) >> 32) - kKeyBias);
+}
+__device__ inline uint32_t hit_key_gid(double k) { return uint32_t(uint64_t(__double_as_longlong(k))); }
+
 template <int K>
 struct HitBuf {
-    uint64_t key[K];  // sorted ascending; kKeyNone marks an empty slot
+    double key[K];  // sorted ascending; kNoHit marks an empty slot
 
     __device__ inline void clear()
     {
 #pragma unroll
-        for (int s = 0; s < K; ++s) key[s] = kKeyNone;
+        for (int s = 0; s < K; ++s) key[s] = kNoHit;
     }
 
     // drop the front entry (static register moves: no dynamic indexing)
@@ -115,18 +135,17 @@ struct HitBuf {
     {
 #pragma unroll
         for (int s = 0; s + 1 < K; ++s) key[s] = key[s + 1];
-        key[K - 1] = kKeyNone;
+        key[K - 1] = kNoHit;
     }
 
-    // sorted insert of k; the last entry falls off (inserting kKeyNone changes nothing)
-    __device__ inline void insert(uint64_t k)
+    // sorted insert of k; the last entry falls off (inserting kNoHit changes nothing)
+    __device__ inline void insert(double k)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            const bool sw = k < key[s];
-            const uint64_t tk = key[s];
-            key[s] = sw ? k : tk;
-            k = sw ? tk : k;
+            const double lo = __builtin_fmin(key[s], k);
+            k = __builtin_fmax(key[s], k);
+            key[s] = lo;
         }
     }
 };
@@ -278,6 +297,8 @@ struct RaySet {
     const float *origin, *dir, *tmax, *bgray, *grad;
     float *out_rgb;
     float4 *state;
+    int32_t *count;  // stored hit lists (optional): composited hits per ray
+    int32_t *ids;    // [hit_cap][n_rays] Gaussian ids in compositing order
     float bg[3];
     int32_t zero_colour;
 };
@@ -286,10 +307,221 @@ struct Ptrs {
     const float *quat, *rgb;
     RaySet set[kMaxSets];
     int32_t *status;
-    uint32_t *queue;
+    uint32_t *queue;  // XCD queue counters (kXcdQueues)
     unsigned long long *counters;
     float *gacc;  // adjoint accumulator, 16 floats per Gaussian (see k_scatter_grads)
 };
+
+// ------------------------------------------------------- shared kernel steps
+
+// Next packet of a wave (wave-uniform; n_packets when there is none). Plain
+// grids take one packet per workgroup; persistent ones first drain the queue
+// of their own XCD's chunk (a compact image region, so that XCD's L2 holds
+// its working set), then take from the other chunks.
+template <typename PT>
+__device__ inline int64_t next_packet(const PT &P, uint32_t *queue, int lane, int xcd, int &qi, int64_t &iter)
+{
+    if (!P.persistent) return iter++ > 0 ? P.n_packets : int64_t(blockIdx.x);
+    while (qi < kXcdQueues) {
+        const int q = (xcd + qi) & (kXcdQueues - 1);
+        uint32_t p = 0;
+        if (lane == 0) p = atomicAdd(queue + q, 1u);
+        p = __builtin_amdgcn_readfirstlane(p);
+        const int64_t g = q * P.chunk + p;
+        if (g < P.n_packets && p < P.chunk) return g;
+        ++qi;
+    }
+    return P.n_packets;
+}
+
+__device__ inline int xcd_id() { return int(__builtin_amdgcn_s_getreg(20 | (0 << 6) | ((4 - 1) << 11))) & (kXcdQueues - 1); }
+
+// A lane's ray of packet `pkt`: its set, index, geometry, t_max and background.
+struct LaneRay {
+    int si;
+    bool valid;
+    int64_t id;
+    Ray ray;
+    float tmax, bgr, bgg, bgb;
+};
+
+template <typename PT>
+__device__ inline LaneRay lane_ray(const PT &P, const Ptrs &ptr, int64_t pkt, int lane)
+{
+    LaneRay L;
+    L.si = (pkt >= P.packets_per_set ? 1 : 0) + (pkt >= 2 * P.packets_per_set ? 1 : 0);
+    const RaySet &S = ptr.set[L.si];
+    const int64_t local = pkt - L.si * P.packets_per_set;
+    L.id = packet_ray(P, P.persistent ? strip_major_packet(P, local, P.strip_tiles) : local, lane, L.valid);
+    L.tmax = kInf;
+    L.bgr = S.bg[0];
+    L.bgg = S.bg[1];
+    L.bgb = S.bg[2];
+    if (L.valid) {
+        L.ray.ox = S.origin[3 * L.id];
+        L.ray.oy = S.origin[3 * L.id + 1];
+        L.ray.oz = S.origin[3 * L.id + 2];
+        L.ray.dx = S.dir[3 * L.id];
+        L.ray.dy = S.dir[3 * L.id + 1];
+        L.ray.dz = S.dir[3 * L.id + 2];
+        if (S.tmax) L.tmax = S.tmax[L.id];
+        if (S.bgray) {
+            L.bgr = S.bgray[3 * L.id];
+            L.bgg = S.bgray[3 * L.id + 1];
+            L.bgb = S.bgray[3 * L.id + 2];
+        }
+    } else {
+        L.ray.ox = L.ray.oy = L.ray.oz = 0.0f;
+        L.ray.dx = L.ray.dy = 0.0f;
+        L.ray.dz = 1.0f;
+    }
+    return L;
+}
+
+// One composited hit (Eq. 3): the record of Gaussian gid is fetched, alpha is
+// recomputed with the leaf test's own arithmetic (so every kernel sees the
+// same alpha bit for bit) and the front-to-back step is applied.
+struct HitData {
+    float4 r0, r1, r2, r3;
+    float al, cr, cg, cb, Tk;
+};
+
+__device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
+                                     const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
+                                     const RenderParams &P, Accum &A, HitData &H)
+{
+    H.al = H.cr = H.cg = H.cb = 0.0f;
+    H.Tk = A.T;
+    if (act) {
+        const int32_t js = inv[gid];
+        H.r0 = records[4 * js + 0];
+        H.r1 = records[4 * js + 1];
+        H.r2 = records[4 * js + 2];
+        H.r3 = records[4 * js + 3];
+        float t1, h2;
+        ellipsoid_hit(ray, H.r0, H.r1, H.r2, H.r3, P.Q, t1, h2);
+        H.al = H.r3.w * __expf(-0.5f * h2);
+        if (!zc) {
+            H.cr = rgb[3 * gid];
+            H.cg = rgb[3 * gid + 1];
+            H.cb = rgb[3 * gid + 2];
+        }
+        composite_step(A, H.al, H.cr, H.cg, H.cb);
+    }
+}
+
+// Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation: for
+// each distinct Gaussian among the active lanes, the lanes holding it are
+// summed (transposed butterfly) and one 14-lane atomic instruction adds the
+// totals to its 64-byte accumulator line.
+//   dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the
+//   remaining colour of the last composited hit is T_final bg, so there
+//   dC/dalpha = T_k (c_k - bg).
+struct LaneGrad {
+    float gr, gg, gb;     // upstream gradient of the pixel
+    float Cor, Cog, Cob;  // final pixel colour (forward state)
+};
+
+template <bool COUNT>
+__device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, uint32_t gid, const Ray &ray,
+                                   const HitData &H, const Accum &A, const LaneGrad &Gd, float bgr, float bgg,
+                                   float bgb, bool zc, const float *__restrict__ quat, float *gacc, int lane,
+                                   uint64_t &c_group)
+{
+    GradOut G;
+#pragma unroll
+    for (int v = 0; v < 14; ++v) G.v[v] = 0.0f;
+    if (act) {
+        float dLda;
+        if (stopped) {
+            dLda = H.Tk * (Gd.gr * (H.cr - bgr) + Gd.gg * (H.cg - bgg) + Gd.gb * (H.cb - bgb));
+        } else {
+            const float rem = Gd.gr * (Gd.Cor - A.Cr) + Gd.gg * (Gd.Cog - A.Cg) + Gd.gb * (Gd.Cob - A.Cb);
+            dLda = H.Tk * (Gd.gr * H.cr + Gd.gg * H.cg + Gd.gb * H.cb) - rem / (1.0f - H.al);
+        }
+        grad_hit(ray, H.r0, H.r1, H.r2, H.r3, quat, gid, dLda, H.al, G);
+        const float wgt = H.al * H.Tk;
+        G.v[11] = zc ? 0.0f : Gd.gr * wgt;
+        G.v[12] = zc ? 0.0f : Gd.gg * wgt;
+        G.v[13] = zc ? 0.0f : Gd.gb * wgt;
+    }
+    const uint64_t lane_bit = 1ull << lane;
+    uint64_t todo = act_mask;
+    while (todo) {
+        const int leader = __builtin_ctzll(todo);
+        const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
+        const uint64_t same = wave_ballot(act && gid == lg);
+        todo &= ~same;
+        if (COUNT) ++c_group;
+        const bool mine = (same & lane_bit) != 0;
+        float in[16];
+#pragma unroll
+        for (int v = 0; v < 14; ++v) in[v] = mine ? G.v[v] : 0.0f;
+        in[14] = 0.0f;
+        in[15] = 0.0f;
+        const float tot = wave_sum16_transposed(in, lane);
+        if ((lane & 3) == 0 && (lane >> 2) < 14) unsafeAtomicAdd(gacc + 16 * int64_t(lg) + (lane >> 2), tot);
+    }
+}
+
+constexpr int32_t kDone = INT32_MIN;
+
+// Wave-uniform descent from `node` through internal nodes to the next leaf
+// (returned as ~leaf) or to the end of the walk (kDone). A child is entered
+// when some live lane's ray overlaps its box within [t_lo, t_hi]; when both
+// are, the one most of those lanes reach first is taken and the other pushed
+// (stack entry k lives in lane k of `stackv`).
+template <int OCT, bool COUNT>
+__device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes, const Slab &sl, uint64_t live_mask,
+                                  float t_lo, float t_hi_w, int lane, int32_t stack_depth, int32_t &sp,
+                                  int32_t &stackv, bool &overflow, uint64_t &c_node, uint64_t &c_lchild)
+{
+    while (node >= 0) {
+        const uint32_t ns = __builtin_amdgcn_readfirstlane(node);
+        const float4 *nd = nodes + 4 * uint64_t(ns);
+        const float4 n0 = nd[0], n1 = nd[1], n2 = nd[2];
+        const int2 lr = *reinterpret_cast<const int2 *>(nd + 3);
+        float ln, lf, rn, rf;
+        child_slabs<OCT>(n0, n1, n2, sl, ln, lf, rn, rf);
+        // [max(near, t_lo), min(widened exit, t_hi)] non-empty
+        const bool hl = fmaxf(ln, t_lo) <= fminf(widen_exit(lf, sl.pad), t_hi_w);
+        const bool hr = fmaxf(rn, t_lo) <= fminf(widen_exit(rf, sl.pad), t_hi_w);
+        const uint64_t bl = live_mask & wave_ballot(hl);
+        const uint64_t br = live_mask & wave_ballot(hr);
+        const int32_t left = lr.x, right = lr.y;
+        const uint32_t nl = uint32_t(__popcll(bl)), nr = uint32_t(__popcll(br));
+        if (COUNT) {
+            ++c_node;
+            c_lchild += nl + nr;
+        }
+        if (nl * nr != 0) {
+            // both entered: the child most of the lanes reach first goes first
+            const uint32_t np = uint32_t(__popcll(bl & (~br | wave_ballot(ln <= rn))));
+            const bool lfirst = 2 * np >= uint32_t(__popcll(bl | br));
+            if (sp >= stack_depth) {
+                overflow = true;
+                return kDone;
+            }
+            stackv = (lane == sp) ? (lfirst ? right : left) : stackv;
+            ++sp;
+            node = lfirst ? left : right;
+        } else if (nl + nr != 0) {
+            node = nl != 0 ? left : right;
+        } else if (sp == 0) {
+            return kDone;
+        } else {
+            --sp;
+            node = __builtin_amdgcn_readlane(stackv, sp);
+        }
+    }
+    return node;
+}
+
+#define RS_DESCEND_CASE(O)                                                                                    \
+    case O:                                                                                                   \
+        node = descend<O, COUNT>(node, nodes, sl, live_mask, t_lo, t_hi_w, lane, P.stack_depth, sp, stackv,   \
+                                 overflow, c_node, c_lchild);                                                 \
+        break;
 
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
 // (512 / waves): the adjoint carries the gradient temporaries as well.
@@ -299,86 +531,68 @@ struct Ptrs {
 #ifndef RS_BWD16_WAVES
 #define RS_BWD16_WAVES 4
 #endif
+#ifndef RS_FWD24_WAVES
+#define RS_FWD24_WAVES 4
+#endif
+#ifndef RS_BWD24_WAVES
+#define RS_BWD24_WAVES 3
+#endif
 constexpr int waves_for(int K, bool bwd)
 {
-    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? 3 : 2))) : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? 4 : 3)));
+    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : 2)))
+               : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : 3)));
 }
 
-template <int K, bool BWD, bool BRUTE>
+template <int K, bool BWD, bool BRUTE, bool COUNT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K, BWD)))) void k_render(
     const float4 *__restrict__ records, const float4 *__restrict__ nodes, const int32_t *__restrict__ gidx,
     const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
 {
     const int lane = threadIdx.x;
-    const uint64_t lane_bit = 1ull << lane;
     int64_t iter_pkt = 0;
-    // work counters (wave-uniform, kept in scalar registers; written when P.count)
+    const int xcd = xcd_id();
+    int qi = 0;
+    // work counters (wave-uniform, scalar registers; only in the COUNT variants)
     uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
              c_group = 0;
     for (;;) {
-        int64_t pkt;
-        if (P.persistent) {
-            uint32_t p = 0;
-            if (lane == 0) p = atomicAdd(ptr.queue, 1u);
-            pkt = __builtin_amdgcn_readfirstlane(p);
-        } else {
-            if (iter_pkt > 0) break;
-            pkt = blockIdx.x;
-        }
-        ++iter_pkt;
+        const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
-        ++c_pkt;
+        if (COUNT) ++c_pkt;
 
-        // the packet's ray set (uniform) and its packet index within the set
-        const int si = (pkt >= P.packets_per_set ? 1 : 0) + (pkt >= 2 * P.packets_per_set ? 1 : 0);
-        const RaySet &S = ptr.set[si];
+        const LaneRay LR = lane_ray(P, ptr, pkt, lane);
+        const RaySet &S = ptr.set[LR.si];
         const bool zc = S.zero_colour != 0;
-        bool valid;
-        const int64_t ray_id = packet_ray(P, pkt - si * P.packets_per_set, lane, valid);
-        Ray ray;
-        float tmax = kInf, bgr = S.bg[0], bgg = S.bg[1], bgb = S.bg[2];
-        if (valid) {
-            ray.ox = S.origin[3 * ray_id];
-            ray.oy = S.origin[3 * ray_id + 1];
-            ray.oz = S.origin[3 * ray_id + 2];
-            ray.dx = S.dir[3 * ray_id];
-            ray.dy = S.dir[3 * ray_id + 1];
-            ray.dz = S.dir[3 * ray_id + 2];
-            if (S.tmax) tmax = S.tmax[ray_id];
-            if (S.bgray) {
-                bgr = S.bgray[3 * ray_id];
-                bgg = S.bgray[3 * ray_id + 1];
-                bgb = S.bgray[3 * ray_id + 2];
-            }
-        } else {
-            ray.ox = ray.oy = ray.oz = 0.0f;
-            ray.dx = ray.dy = 0.0f;
-            ray.dz = 1.0f;
-        }
+        const bool valid = LR.valid;
+        const int64_t ray_id = LR.id;
+        const Ray ray = LR.ray;
+        const float tmax = LR.tmax, bgr = LR.bgr, bgg = LR.bgg, bgb = LR.bgb;
         const Slab sl = make_slab(ray);
-        const WaveSigns wsg = wave_signs(sl, valid);
+        const int oct = wave_octant(sl, valid);
 
         Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
         bool live = valid && P.n_gauss > 0 && tmax > P.t_min;
-        uint64_t last = 0;  // keys of this round must exceed it
-        float gr = 0.0f, gg = 0.0f, gb = 0.0f, Cor = 0.0f, Cog = 0.0f, Cob = 0.0f;
+        double last = -kNoHit;  // keys of this round must exceed it
+        LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (BWD && valid) {
-            gr = S.grad[3 * ray_id];
-            gg = S.grad[3 * ray_id + 1];
-            gb = S.grad[3 * ray_id + 2];
+            Gd.gr = S.grad[3 * ray_id];
+            Gd.gg = S.grad[3 * ray_id + 1];
+            Gd.gb = S.grad[3 * ray_id + 2];
             const float4 s = S.state[ray_id];
-            Cor = s.x;
-            Cog = s.y;
-            Cob = s.z;
-            if (gr == 0.0f && gg == 0.0f && gb == 0.0f) live = false;
+            Gd.Cor = s.x;
+            Gd.Cog = s.y;
+            Gd.Cob = s.z;
+            if (Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f) live = false;
+            // with stored hit lists the list kernel takes every ray whose list is complete
+            if (S.count && S.count[ray_id] <= P.hit_cap) live = false;
         }
         bool overflow = false;
 
-        while (__ballot(live)) {
+        while (wave_ballot(live)) {
             HitBuf<K> hb;
             hb.clear();
-            ++c_round;
-            const float t_lo = last == 0 ? P.t_min : fmaxf(P.t_min, key_t(last));
+            if (COUNT) ++c_round;
+            const float t_lo = last == -kNoHit ? P.t_min : fmaxf(P.t_min, hit_key_t(last));
             float t_hi_w = widen(tmax, sl.pad);
 
             auto leaf = [&](int64_t j) {
@@ -388,22 +602,22 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const uint32_t gid = uint32_t(gidx[js]);
                 float t1 = 0.0f, h2 = 0.0f;
                 bool cand = false;
-                uint64_t k = kKeyNone;
+                double k = kNoHit;
                 if (live && ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2)) {
-                    k = make_key(t1, gid);
+                    k = hit_key(t1, gid);
                     cand = t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
                 }
-                const uint64_t cmask = __ballot(cand);
-                if (P.count) {
+                const uint64_t cmask = wave_ballot(cand);
+                if (COUNT) {
                     ++c_leaf;
-                    c_lleaf += __popcll(__ballot(live));
+                    c_lleaf += __popcll(wave_ballot(live));
                     c_lbuf += __popcll(cmask);
                 }
                 if (cmask) {
                     // every lane runs the insertion network; lanes without a candidate insert
                     // the empty key, which moves nothing
-                    hb.insert(cand ? k : kKeyNone);
-                    if (hb.key[K - 1] != kKeyNone) t_hi_w = widen(fminf(tmax, key_t(hb.key[K - 1])), sl.pad);
+                    hb.insert(cand ? k : kNoHit);
+                    if (hb.key[K - 1] != kNoHit) t_hi_w = widen(fminf(tmax, hit_key_t(hb.key[K - 1])), sl.pad);
                 }
             };
 
@@ -412,46 +626,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             } else {
                 // While-while traversal: descend internal nodes until a leaf is reached (or the
                 // stack runs dry), then test that leaf; the hit buffer changes only in the leaf step.
-                constexpr int32_t kDone = INT32_MIN;
+                // The descent is specialised on the wave's direction octant.
                 int32_t node = P.root;
                 int32_t sp = 0;
                 int32_t stackv = 0;
+                const uint64_t live_mask = wave_ballot(live);
                 for (;;) {
-                    while (node >= 0) {
-                        const int64_t ns = __builtin_amdgcn_readfirstlane(node);
-                        const float4 n0 = nodes[4 * ns], n1 = nodes[4 * ns + 1], n2 = nodes[4 * ns + 2],
-                                     n3 = nodes[4 * ns + 3];
-                        float ln, lf, rn, rf;
-                        child_slabs(n0, n1, n2, sl, wsg, ln, lf, rn, rf);
-                        const bool hl = live && fmaxf(ln, t_lo) <= fminf(widen(lf, sl.pad), t_hi_w);
-                        const bool hr = live && fmaxf(rn, t_lo) <= fminf(widen(rf, sl.pad), t_hi_w);
-                        const uint64_t bl = __ballot(hl), br = __ballot(hr);
-                        const int32_t left = __float_as_int(n3.x), right = __float_as_int(n3.y);
-                        if (P.count) {
-                            ++c_node;
-                            c_lchild += __popcll(bl) + __popcll(br);
-                        }
-                        if (bl && br) {
-                            const uint64_t pref = __ballot(hl && (!hr || ln <= rn));
-                            const bool lfirst = 2 * __popcll(pref) >= __popcll(bl | br);
-                            if (sp >= P.stack_depth) {
-                                overflow = true;
-                                node = kDone;
-                                break;
-                            }
-                            stackv = (lane == sp) ? (lfirst ? right : left) : stackv;  // lane sp holds entry sp
-                            ++sp;
-                            node = lfirst ? left : right;
-                        } else if (bl) {
-                            node = left;
-                        } else if (br) {
-                            node = right;
-                        } else if (sp == 0) {
-                            node = kDone;
-                        } else {
-                            --sp;
-                            node = __builtin_amdgcn_readlane(stackv, sp);
-                        }
+                    switch (oct) {
+                        RS_DESCEND_CASE(0)
+                        RS_DESCEND_CASE(1)
+                        RS_DESCEND_CASE(2)
+                        RS_DESCEND_CASE(3)
+                        RS_DESCEND_CASE(4)
+                        RS_DESCEND_CASE(5)
+                        RS_DESCEND_CASE(6)
+                        RS_DESCEND_CASE(7)
+                    default:
+                        RS_DESCEND_CASE(kMixedOctant)
                     }
                     if (node == kDone) break;
                     leaf(~node);
@@ -468,82 +659,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 
             // composite this round's hits front to back; alpha is recomputed from the record
             // with the leaf test's own arithmetic. The buffer is consumed from its front.
-            const uint64_t round_last = hb.key[K - 1];
+            const double round_last = hb.key[K - 1];
             bool more = true;
             for (int s = 0; s < K; ++s) {
-                const uint64_t key_s = hb.key[0];
+                const double key_s = hb.key[0];
                 hb.pop_front();
-                const bool act = more && live && key_s != kKeyNone;
-                const uint64_t act_mask = __ballot(act);
+                const bool act = more && live && key_s != kNoHit;
+                const uint64_t act_mask = wave_ballot(act);
                 more = act_mask != 0;
                 if (!more) break;
-                c_lcomp += __popcll(act_mask);
-                const uint32_t gid = uint32_t(key_s & 0xffffffffu);
-                float al = 0.0f, cr = 0.0f, cg = 0.0f, cb = 0.0f;
-                float4 r0, r1, r2, r3;
-                const float Tk = A.T;
-                if (act) {
-                    const int32_t js = inv[gid];
-                    r0 = records[4 * js + 0];
-                    r1 = records[4 * js + 1];
-                    r2 = records[4 * js + 2];
-                    r3 = records[4 * js + 3];
-                    float t1, h2;
-                    ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2);
-                    al = r3.w * __expf(-0.5f * h2);
-                    if (!zc) {
-                        cr = ptr.rgb[3 * gid];
-                        cg = ptr.rgb[3 * gid + 1];
-                        cb = ptr.rgb[3 * gid + 2];
-                    }
-                    composite_step(A, al, cr, cg, cb);
-                }
+                if (COUNT) c_lcomp += __popcll(act_mask);
+                const uint32_t gid = hit_key_gid(key_s);
+                HitData H;
+                composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
+                if (!BWD && act && S.ids && A.n <= P.hit_cap)
+                    S.ids[int64_t(A.n - 1) * P.n_rays + ray_id] = int32_t(gid);
                 const bool stopped = act && stop_after(A, P);
-                if (BWD) {
-                    GradOut G;
-#pragma unroll
-                    for (int v = 0; v < 14; ++v) G.v[v] = 0.0f;
-                    if (act) {
-                        // dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the remaining
-                        // colour of the last composited hit is T_final bg, so there dC/dalpha = T_k (c_k - bg)
-                        float dLda;
-                        if (stopped) {
-                            dLda = Tk * (gr * (cr - bgr) + gg * (cg - bgg) + gb * (cb - bgb));
-                        } else {
-                            const float rem = gr * (Cor - A.Cr) + gg * (Cog - A.Cg) + gb * (Cob - A.Cb);
-                            dLda = Tk * (gr * cr + gg * cg + gb * cb) - rem / (1.0f - al);
-                        }
-                        grad_hit(ray, r0, r1, r2, r3, ptr.quat, gid, dLda, al, G);
-                        const float wgt = al * Tk;
-                        G.v[11] = zc ? 0.0f : gr * wgt;
-                        G.v[12] = zc ? 0.0f : gg * wgt;
-                        G.v[13] = zc ? 0.0f : gb * wgt;
-                    }
-                    // wave aggregation: for each distinct Gaussian among the active lanes, the
-                    // lanes holding it are summed (transposed butterfly) and one 14-lane atomic
-                    // instruction adds the totals to its 64-byte accumulator line
-                    uint64_t todo = act_mask;
-                    while (todo) {
-                        const int leader = __builtin_ctzll(todo);
-                        const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
-                        const uint64_t same = __ballot(act && gid == lg);
-                        todo &= ~same;
-                        ++c_group;
-                        const bool mine = (same & lane_bit) != 0;
-                        float in[16];
-#pragma unroll
-                        for (int v = 0; v < 14; ++v) in[v] = mine ? G.v[v] : 0.0f;
-                        in[14] = 0.0f;
-                        in[15] = 0.0f;
-                        const float tot = wave_sum16_transposed(in, lane);
-                        if ((lane & 3) == 0 && (lane >> 2) < 14)
-                            unsafeAtomicAdd(ptr.gacc + 16 * int64_t(lg) + (lane >> 2), tot);
-                    }
-                }
+                if (BWD)
+                    adjoint_hit<COUNT>(act, act_mask, stopped, gid, ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
+                                       lane, c_group);
                 if (stopped) live = false;
             }
             // a lane whose buffer did not fill has consumed all its hits
-            if (live && round_last == kKeyNone) live = false;
+            if (live && round_last == kNoHit) live = false;
             last = round_last;
         }
 
@@ -554,9 +692,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             if (S.state) S.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
                                                            __builtin_fmaf(A.T, bgg, A.Cg),
                                                            __builtin_fmaf(A.T, bgb, A.Cb), A.T);
+            if (S.count) S.count[ray_id] = A.n;
         }
     }
-    if (P.count && lane == 0 && c_pkt > 0) {
+    if (COUNT && lane == 0 && c_pkt > 0) {
         atomicAdd(ptr.counters + 0, (unsigned long long)c_pkt);
         atomicAdd(ptr.counters + 1, (unsigned long long)c_node);
         atomicAdd(ptr.counters + 2, (unsigned long long)c_leaf);
@@ -566,6 +705,62 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
         atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
         atomicAdd(ptr.counters + 8, (unsigned long long)c_group);
+    }
+}
+
+// Adjoint from stored hit lists: the forward recorded, per ray, the ids of
+// the Gaussians it composited in order; the adjoint replays that list (no
+// traversal, no hit buffer) with the forward's own per-hit arithmetic. Rays
+// whose list overflowed the capacity are left to the traversal adjoint.
+template <bool COUNT>
+__global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ records,
+                                                     const int32_t *__restrict__ inv, const Ptrs ptr,
+                                                     const RenderParams P)
+{
+    const int lane = threadIdx.x;
+    int64_t iter_pkt = 0;
+    const int xcd = xcd_id();
+    int qi = 0;
+    uint64_t c_pkt = 0, c_lcomp = 0, c_group = 0;
+    for (;;) {
+        const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
+        if (pkt >= P.n_packets) break;
+        if (COUNT) ++c_pkt;
+        const LaneRay LR = lane_ray(P, ptr, pkt, lane);
+        const RaySet &S = ptr.set[LR.si];
+        const bool zc = S.zero_colour != 0;
+        int32_t cnt = 0;
+        LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        if (LR.valid) {
+            cnt = S.count[LR.id];
+            Gd.gr = S.grad[3 * LR.id];
+            Gd.gg = S.grad[3 * LR.id + 1];
+            Gd.gb = S.grad[3 * LR.id + 2];
+            const float4 st = S.state[LR.id];
+            Gd.Cor = st.x;
+            Gd.Cog = st.y;
+            Gd.Cob = st.z;
+        }
+        const bool live = LR.valid && cnt > 0 && cnt <= P.hit_cap && P.n_gauss > 0 &&
+                          !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
+        Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
+        for (int32_t k = 0;; ++k) {
+            const bool act = live && k < cnt;
+            const uint64_t act_mask = wave_ballot(act);
+            if (!act_mask) break;
+            if (COUNT) c_lcomp += __popcll(act_mask);
+            const uint32_t gid = act ? uint32_t(S.ids[int64_t(k) * P.n_rays + LR.id]) : 0u;
+            HitData H;
+            composite_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P, A, H);
+            const bool stopped = act && stop_after(A, P);
+            adjoint_hit<COUNT>(act, act_mask, stopped, gid, LR.ray, H, A, Gd, LR.bgr, LR.bgg, LR.bgb, zc, ptr.quat,
+                               ptr.gacc, lane, c_group);
+        }
+    }
+    if (COUNT && lane == 0 && c_pkt > 0) {
+        atomicAdd(ptr.counters + 9, (unsigned long long)c_pkt);
+        atomicAdd(ptr.counters + 10, (unsigned long long)c_lcomp);
+        atomicAdd(ptr.counters + 11, (unsigned long long)c_group);
     }
 }
 
@@ -607,7 +802,7 @@ __global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict_
 
 __global__ void k_zero_queue(uint32_t *q)
 {
-    if (threadIdx.x == 0) *q = 0u;
+    if (threadIdx.x < kXcdQueues) q[threadIdx.x] = 0u;
 }
 
 static void zero(float *p, int64_t n, hipStream_t st)
@@ -618,21 +813,26 @@ static void zero(float *p, int64_t n, hipStream_t st)
     k_zero_f32<<<int(blocks), 256, 0, st>>>(p, n);
 }
 
+template <int K, bool BWD>
+static void launch_kb(int grid, const float4 *records, const float4 *nodes, const int32_t *gidx, const int32_t *inv,
+                      const Ptrs &ptr, const RenderParams &P, hipStream_t st)
+{
+    if (P.brute)
+        k_render<K, BWD, true, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+    else if (P.count)
+        k_render<K, BWD, false, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+    else
+        k_render<K, BWD, false, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
+}
+
 template <int K>
 static void launch_k(bool bwd, int grid, const float4 *records, const float4 *nodes, const int32_t *gidx,
                      const int32_t *inv, const Ptrs &ptr, const RenderParams &P, hipStream_t st)
 {
-    if (P.brute) {
-        if (bwd)
-            k_render<K, true, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-        else
-            k_render<K, false, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-    } else {
-        if (bwd)
-            k_render<K, true, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-        else
-            k_render<K, false, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-    }
+    if (bwd)
+        launch_kb<K, true>(grid, records, nodes, gidx, inv, ptr, P, st);
+    else
+        launch_kb<K, false>(grid, records, nodes, gidx, inv, ptr, P, st);
 }
 
 void zero_gacc(const BvhDesc &D, hipStream_t st)
@@ -652,7 +852,7 @@ void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st)
 
 // One launch over one or two ray sets sharing a layout (same count, same views).
 int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets,
-                bool bwd, hipStream_t st)
+                bool bwd, hipStream_t st, bool list_adjoint)
 {
     Layout L = make_layout(D.n);
     char *ws = D.ws;
@@ -675,6 +875,9 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     const int64_t packets = plan_packets(P, rays, tile_shift_of(p));
     P.packets_per_set = packets;
     P.n_packets = packets * nsets;
+    P.strip_tiles = kStripTiles;
+    P.hit_cap = sets[0].count ? p->hit_list : 0;
+    P.chunk = (P.n_packets + kXcdQueues - 1) / kXcdQueues;
 
     Ptrs ptr{};
     ptr.quat = g->quat;
@@ -689,18 +892,20 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
         R.grad = E.grad;
         R.out_rgb = E.out_rgb;
         R.state = reinterpret_cast<float4 *>(E.state);
+        R.count = E.count;
+        R.ids = E.ids;
         for (int c = 0; c < 3; ++c) R.bg[c] = E.bg[c];
         R.zero_colour = E.zero_colour;
     }
     ptr.status = &h->status;
-    ptr.queue = &h->queue;
+    ptr.queue = h->xq;
     ptr.counters = reinterpret_cast<unsigned long long *>(h->counters);
     ptr.gacc = reinterpret_cast<float *>(ws + L.gacc);
 
     if (P.n_packets > 0) {
         int grid;
         if (P.persistent) {
-            k_zero_queue<<<1, 64, 0, st>>>(&h->queue);
+            k_zero_queue<<<1, 64, 0, st>>>(h->xq);
             int dev = 0, cus = 256;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -715,13 +920,20 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
         const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
         // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
         // the default is the fastest measured size on MI355X
-        const int K = p->kbuf > 0 ? p->kbuf : 24;
-        switch (K) {
-        case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-        case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-        case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-        case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-        default: return RS_ERR_INVALID_ARG;
+        if (list_adjoint) {
+            if (P.count)
+                k_adjoint_list<true><<<grid, kWave, 0, st>>>(records, inv, ptr, P);
+            else
+                k_adjoint_list<false><<<grid, kWave, 0, st>>>(records, inv, ptr, P);
+        } else {
+            const int K = p->kbuf > 0 ? p->kbuf : 24;
+            switch (K) {
+            case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            default: return RS_ERR_INVALID_ARG;
+            }
         }
     }
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
@@ -738,10 +950,24 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     S.grad = grad;
     for (int c = 0; c < 3; ++c) S.bg[c] = p->bg[c];
     S.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
-    if (bwd) zero_gacc(D, st);
-    int e = launch_sets(D, g, p, 1, &S, bwd, st);
-    if (e) return e;
-    if (bwd) scatter_gacc(D, grads, st);
+    if (state && p->hit_list > 0 && rays->n > 0) {
+        const StateLayout sl = state_layout(rays->n, p->hit_list);
+        S.count = reinterpret_cast<int32_t *>(static_cast<char *>(state) + sl.count);
+        S.ids = reinterpret_cast<int32_t *>(static_cast<char *>(state) + sl.ids);
+    }
+    int e;
+    if (!bwd) return launch_sets(D, g, p, 1, &S, false, st);
+    zero_gacc(D, st);
+    if (S.count) {
+        // stored lists first; the traversal adjoint then takes only the rays whose list
+        // overflowed, which can happen only when K_max exceeds the capacity
+        if ((e = launch_sets(D, g, p, 1, &S, true, st, true))) return e;
+        if (p->max_hits == 0 || p->max_hits > p->hit_list)
+            if ((e = launch_sets(D, g, p, 1, &S, true, st))) return e;
+    } else {
+        if ((e = launch_sets(D, g, p, 1, &S, true, st))) return e;
+    }
+    scatter_gacc(D, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 

@@ -26,6 +26,7 @@ class Params:
     kbuf: int = 0
     stack_depth: int = 0
     tile_width: int = 0
+    hit_list: int = 0
 
     def c(self):
         p = L.rs_params()
@@ -36,6 +37,7 @@ class Params:
         p.kbuf = int(self.kbuf)
         p.stack_depth = int(self.stack_depth)
         p.tile_width = int(self.tile_width)
+        p.hit_list = int(self.hit_list)
         return p
 
 
@@ -117,6 +119,24 @@ class BVH:
         self.n, self.Q, self.workspace, self.desc = n, Q, workspace, desc
 
 
+def state_bytes(n, params=None):
+    pc = params.c() if params is not None else None
+    return int(L.lib().rs_ray_state_bytes(int(n), C.byref(pc) if pc is not None else None))
+
+
+def new_state(n, params, device="cuda"):
+    """Ray state for render_fwd / render_bwd: float32 [n, 4] (colour, T) when
+    params.hit_list == 0, else a flat buffer whose first 4 n floats are that."""
+    if not params.hit_list:
+        return torch.empty((n, 4), dtype=torch.float32, device=device)
+    return torch.empty(max(state_bytes(n, params) // 4, 64), dtype=torch.float32, device=device)
+
+
+def state_colour(state, n):
+    """The [n, 4] (final colour, final transmittance) part of a ray state."""
+    return state if state.dim() == 2 else state[:4 * n].view(n, 4)
+
+
 def workspace_bytes(n):
     return int(L.lib().rs_bvh_workspace_bytes(int(n)))
 
@@ -139,7 +159,7 @@ def render_fwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, out=None, sta
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
     if want_state and state is None:
-        state = torch.empty((n, 4), dtype=torch.float32, device=rays.origin.device)
+        state = new_state(n, params, rays.origin.device)
     gc, rc, pc = g.c(), rays.c(), params.c()
     L.check(lib.rs_render_fwd(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(out), _ptr(state),
                               _stream()), "rs_render_fwd")
@@ -163,7 +183,7 @@ def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, sta
 def _params_from_c(cp, like):
     return Params(Q=like.Q, eps1=like.eps1, t_min=like.t_min, max_hits=like.max_hits, bg=tuple(like.bg),
                   flags=int(cp.flags), kbuf=int(cp.kbuf), stack_depth=int(cp.stack_depth),
-                  tile_width=int(cp.tile_width))
+                  tile_width=int(cp.tile_width), hit_list=int(cp.hit_list))
 
 
 def autotune(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb=None, reps=2):
@@ -172,7 +192,7 @@ def autotune(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb=None, 
     n = rays.n
     dev = rays.origin.device
     out = torch.empty((n, 3), dtype=torch.float32, device=dev)
-    state = torch.empty((n, 4), dtype=torch.float32, device=dev)
+    state = new_state(n, params, dev)
     gr = None
     keep = None
     if grad_rgb is not None:

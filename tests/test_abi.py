@@ -69,7 +69,12 @@ def test_defaults_and_strings(L):
     assert abs(p.Q - 11.3449) < 1e-5 and abs(p.eps1 - 1e-4) < 1e-9 and p.max_hits == 512 and p.flags == 0
     for code in range(0, -8, -1):
         assert lib.rs_status_string(code)
-    assert lib.rs_ray_state_bytes(10) == 160
+    assert lib.rs_ray_state_bytes(10, None) == 160
+    q = L.rs_params()
+    lib.rs_default_params(C.byref(q))
+    q.hit_list = 8
+    # colour/T, then 256-byte aligned count[n] and ids[C][n]
+    assert lib.rs_ray_state_bytes(10, C.byref(q)) == 256 + 256 + 8 * 10 * 4
     a, b = lib.rs_bvh_workspace_bytes(1000), lib.rs_bvh_workspace_bytes(100000)
     assert 0 < a < b and b % 256 == 0
 
@@ -91,7 +96,8 @@ def test_invalid_arguments_are_rejected(L):
     assert lib.rs_build_bvh(C.byref(g), C.byref(p), fake, 100, C.byref(out), None) == L.RS_ERR_WORKSPACE
     # bad knobs
     for field, val in (("Q", 0.0), ("eps1", -1.0), ("max_hits", -3), ("kbuf", 12), ("stack_depth", 65),
-                       ("flags", 1 << 9)):
+                       ("flags", 1 << 9), ("t_min", -1.0), ("tile_width", 12), ("hit_list", -1),
+                       ("hit_list", 5000)):
         q = L.rs_params()
         lib.rs_default_params(C.byref(q))
         setattr(q, field, val)

@@ -67,12 +67,13 @@ def test_batched_views_equal_per_view_launches():
     assert R.read_status(bvh) == 0
 
 
-def test_autotune_picks_a_listed_candidate_with_identical_output():
-    print("case autotune", flush=True)
+@pytest.mark.parametrize("hit_list", [0, 64])
+def test_autotune_picks_a_listed_candidate_with_identical_output(hit_list):
+    print("case autotune", hit_list, flush=True)
     G, R = _g()
     sc, o, d, views = _multiview(8000)
     g = G.gaussians(sc)
-    p = R.Params()
+    p = R.Params(hit_list=hit_list)
     bvh = R.build_bvh(g, p)
     rays = G.rays_of(o, d, views)
     ref, state = R.render_fwd(bvh, g, rays, p)
@@ -89,7 +90,7 @@ def test_autotune_picks_a_listed_candidate_with_identical_output():
     best_b = min(rows, key=lambda r: r["ms_bwd"])
     assert (pb.kbuf, bool(pb.flags & 2), pb.tile_width) == (best_b["kbuf"], best_b["persistent"],
                                                             best_b["tile_width"])
-    assert pf.Q == p.Q and pf.eps1 == p.eps1 and pf.max_hits == p.max_hits
+    assert pf.Q == p.Q and pf.eps1 == p.eps1 and pf.max_hits == p.max_hits and pf.hit_list == p.hit_list
     out, state2 = R.render_fwd(bvh, g, rays, pf)
     np.testing.assert_array_equal(out.cpu().numpy(), ref.cpu().numpy())
     _grads_close(R.render_bwd(bvh, g, rays, pb, grad, state2), ref_g)
@@ -98,20 +99,21 @@ def test_autotune_picks_a_listed_candidate_with_identical_output():
     assert len(rows2) == 8 and pb2 == pf2 and all(r["ms_bwd"] == 0 for r in rows2)
 
 
-def test_graph_captured_training_step_replays_match_eager():
+@pytest.mark.parametrize("hit_list", [0, 128])
+def test_graph_captured_training_step_replays_match_eager(hit_list):
     """Capture BVH rebuild + forward + L1 gradient + adjoint in one HIP graph;
     replays (with eager work and parameter updates in between) equal the eager
     step: forward bitwise, gradients to atomic-order rounding."""
-    print("case graph step", flush=True)
+    print("case graph step", hit_list, flush=True)
     G, R = _g()
     sc, o, d, views = _multiview(20000)
     g = G.gaussians(sc)
-    p = R.Params()
+    p = R.Params(hit_list=hit_list)
     rays = G.rays_of(o, d, views)
     n, nr = sc.n, o.shape[0]
     ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device="cuda")
     out = torch.empty((nr, 3), device="cuda")
-    state = torch.empty((nr, 4), device="cuda")
+    state = R.new_state(nr, p)
     grads = tuple(torch.empty_like(t) for t in (g.mean, g.scale, g.quat, g.opacity, g.rgb))
     target = torch.rand((nr, 3), device="cuda")
 

@@ -139,3 +139,73 @@ def test_config2_l1_loss_gradients_sampled():
     sel = np.sort(rng.choice(o.shape[0], 1200, replace=False))
     grad = np.sign(out[sel] - tgt[sel]) / (3.0 * o.shape[0])
     _grad_parity(w["scene"], o[sel], d[sel], grad, R.Params(), views=None, label="config2 sampled")
+
+
+# ------------------------------------------------- stored hit lists (store vs recompute)
+
+def _fwd_bwd(R, G, sc, o, d, p, views, grad):
+    out, state, status, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
+    assert status == 0
+    gg = R.render_bwd(bvh, g, rays, p, G.dev(np.float32(grad)), torch.from_numpy(state).cuda())
+    torch.cuda.synchronize()
+    return out, state, [t.cpu().numpy().astype(np.float64) for t in gg], bvh
+
+
+@pytest.mark.parametrize("cap,max_hits", [(512, 512), (64, 512), (4, 0), (16, 64)])
+def test_stored_hit_lists_match_recompute(cap, max_hits):
+    """The list-replay adjoint (with traversal for rays whose list overflows)
+    gives the recomputing adjoint's gradients; the forward is unchanged and its
+    lists hold exactly the composited ids."""
+    print("case hit lists", cap, max_hits, flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    sc = w["scene"]
+    rng = np.random.default_rng(11)
+    grad = rng.normal(size=(o.shape[0], 3))
+    out0, st0, g0, _ = _fwd_bwd(R, G, sc, o, d, R.Params(max_hits=max_hits), views, grad)
+    p = R.Params(max_hits=max_hits, hit_list=cap)
+    out1, st1, g1, bvh = _fwd_bwd(R, G, sc, o, d, p, views, grad)
+    np.testing.assert_array_equal(out1, out0)
+    n = o.shape[0]
+    np.testing.assert_array_equal(st1[:4 * n].reshape(n, 4), st0)
+    for k, a, b in zip(GROUPS, g1, g0):
+        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), k
+    # the stored ids are the oracle's composited hits, in order, for rays whose hit set is unambiguous
+    raw = st1.view(np.int32)
+    base = (n * 16 + 255) // 256 * 256 // 4
+    counts = raw[base:base + n]
+    ids_off = ((n * 16 + 255) // 256 * 256 + n * 4 + 255) // 256 * 256 // 4
+    ids = raw[ids_off:ids_off + cap * n].reshape(cap, n)
+    op = G.oracle_params(O, p)
+    unamb = _unambiguous(sc, o, d, op)
+    _, _, L = O.render_fwd(sc, o, d, op)
+    checked = 0
+    for r in np.nonzero(unamb)[0][::17]:
+        idx, _, _, _ = O.ray_hits(sc, o, d, int(r), op)
+        assert counts[r] == L[r], r
+        m = int(min(L[r], cap))
+        np.testing.assert_array_equal(ids[:m, r], idx[:m])
+        checked += 1
+    assert checked > 50
+    if cap >= 64 and max_hits <= cap:
+        assert counts.max() <= cap
+
+
+def test_stored_hit_lists_oracle_parity_and_counters():
+    print("case hit lists parity", flush=True)
+    G, R = _g()
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    rng = np.random.default_rng(12)
+    p = R.Params(hit_list=128)
+    _grad_parity(w["scene"], o, d, rng.normal(size=(o.shape[0], 3)), p, views=views, label="lists")
+    # work counters: the list adjoint replays exactly the forward's composited hits
+    pc = R.Params(hit_list=512, flags=8)
+    out, state, _, (bvh, g, rays) = G.render(w["scene"], o, d, pc, views=views)
+    cf = R.read_counters(bvh)
+    R.render_bwd(bvh, g, rays, pc, G.dev(np.float32(rng.normal(size=(o.shape[0], 3)))),
+                 torch.from_numpy(state).cuda())
+    cb = R.read_counters(bvh)
+    assert cb["r10"] == cf["lane_composited"] > 0
+    assert cb["lane_composited"] == cf["lane_composited"]  # no traversal adjoint ran
