@@ -90,9 +90,9 @@ def main():
     g = R.Gaussians(*(t(a) for a in sc.arrays()))
     rays = R.Rays(t(o), t(d), views=views)
     fixed = args.kbuf or args.persistent or args.tile_width
-    # the mesh renders always recompute (their three ray sets keep no lists)
+    # the mesh render keeps lists for its three ray sets in the frame: capacity capped at 256
     base = R.Params(kbuf=args.kbuf, flags=2 if args.persistent else 0, tile_width=args.tile_width,
-                    hit_list=args.hit_list if mesh_np is None else 0)
+                    hit_list=args.hit_list if mesh_np is None else min(args.hit_list, 256))
     nr = o.shape[0]
     n = sc.n
 
@@ -103,7 +103,7 @@ def main():
         mbvh = R.build_mesh_bvh(dm)
         L = w["light"]
         shading = R.Shading(light=(float(L[0]), float(L[1]), float(L[2])))
-    frame = R.mesh_frame(nr) if mesh_np is not None else None
+    frame = R.mesh_frame(nr, base) if mesh_np is not None else None
 
     def render(bvh, gs, p, out, state=None):
         if mesh_np is not None:

@@ -109,7 +109,7 @@ typedef struct {
  * Gaussians it composites (4 C bytes per ray of ray state) and the adjoint
  * replays those lists instead of traversing the BVH again; rays that
  * composite more than C hits are re-traversed. The gradients are the same
- * (up to float atomic order). Ignored by the mesh renders. */
+ * (up to float atomic order). The mesh renders keep their lists in the frame. */
 typedef struct {
     float Q, eps1, t_min;
     int32_t max_hits;
@@ -265,8 +265,10 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
                   int32_t *tri, void *stream);
 
 /* Per-frame device scratch of the mesh render for n rays (secondary rays,
- * their states and the terms the adjoint needs), 256-byte aligned. */
-size_t rs_mesh_frame_bytes(int64_t n_rays);
+ * their states, the terms the adjoint needs and, with p->hit_list = C > 0,
+ * the stored hit lists of the three ray sets: 3 (C + 1) 4 bytes per ray),
+ * 256-byte aligned. p may be NULL (C = 0). */
+size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p);
 
 /* Forward render of Gaussians + mesh with reflection and shadow rays. After
  * the triangle traces, the Gaussians along the primary, reflection and shadow
@@ -277,7 +279,8 @@ int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
                        void *stream);
 
 /* Adjoint of rs_render_mesh_fwd with respect to the Gaussian parameters
- * (the mesh and the light carry no gradient). Overwrites `out`. */
+ * (the mesh and the light carry no gradient). Overwrites `out`. Needs the
+ * frame of the forward call, made with the same params (hit_list included). */
 int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
                        const rs_shading *sh, const rs_rays *rays, const rs_params *p, const float *grad_rgb,
                        void *frame, rs_grads *out, void *stream);

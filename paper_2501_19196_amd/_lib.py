@@ -123,7 +123,7 @@ def lib():
     L.rs_build_mesh_bvh.restype = C.c_int
     L.rs_trace_mesh.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_rays), P, C.c_int, P, P, P]
     L.rs_trace_mesh.restype = C.c_int
-    L.rs_mesh_frame_bytes.argtypes = [C.c_int64]
+    L.rs_mesh_frame_bytes.argtypes = [C.c_int64, C.POINTER(rs_params)]
     L.rs_mesh_frame_bytes.restype = C.c_size_t
     L.rs_render_mesh_fwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_mesh),
                                      C.POINTER(rs_shading), C.POINTER(rs_rays), C.POINTER(rs_params), P, P, P]

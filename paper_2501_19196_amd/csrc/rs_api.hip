@@ -206,7 +206,10 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
                              static_cast<hipStream_t>(stream));
 }
 
-size_t rs_mesh_frame_bytes(int64_t n_rays) { return n_rays >= 0 ? mesh_frame_bytes(n_rays) : 0; }
+size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p)
+{
+    return n_rays >= 0 ? mesh_frame_bytes(n_rays, p && p->hit_list > 0 ? p->hit_list : 0) : 0;
+}
 
 int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
                        const rs_shading *sh, const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame,

@@ -159,10 +159,12 @@ struct Frame {
     float *shade;    // [n][3] background of the primary adjoint
     float4 *st_pb;   // [n] primary state with the final colour
     float *g_r, *g_s;  // [n][3] upstream gradients of the secondary rays
+    int32_t *cnt[3];   // stored hit lists of the three ray sets (hit_list > 0)
+    int32_t *ids[3];   // [cap][n] each
     size_t total;
 };
 
-static Frame frame_layout(char *base, int64_t n)
+static Frame frame_layout(char *base, int64_t n, int32_t cap)
 {
     Frame F{};
     size_t off = 0;
@@ -197,6 +199,10 @@ static Frame frame_layout(char *base, int64_t n)
     F.st_pb = reinterpret_cast<float4 *>(take(4 * f));
     F.g_r = reinterpret_cast<float *>(take(3 * f));
     F.g_s = reinterpret_cast<float *>(take(3 * f));
+    for (int k = 0; k < 3; ++k) {
+        F.cnt[k] = cap > 0 ? reinterpret_cast<int32_t *>(take(f)) : nullptr;
+        F.ids[k] = cap > 0 ? reinterpret_cast<int32_t *>(take(f * size_t(cap))) : nullptr;
+    }
     F.total = off;
     return F;
 }
@@ -368,7 +374,7 @@ int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limi
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 
-size_t mesh_frame_bytes(int64_t n) { return frame_layout(nullptr, n).total; }
+size_t mesh_frame_bytes(int64_t n, int32_t cap) { return frame_layout(nullptr, n, cap).total; }
 
 static ShadeConst shade_const(const rs_shading *sh, const rs_params *p)
 {
@@ -408,6 +414,8 @@ static void mesh_sets(const Frame &F, const rs_rays *rays, rs_rays sets_rays[3],
     for (int k = 0; k < 3; ++k) {
         S[k] = SetDesc{};
         S[k].rays = &sets_rays[k];
+        S[k].count = F.cnt[k];
+        S[k].ids = F.ids[k];
     }
     if (bwd) {
         S[0].state = F.st_pb;  // final colour of the pixel, with the shade as background
@@ -431,7 +439,7 @@ int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, c
 {
     const int64_t n = rays->n;
     if (n == 0) return RS_OK;
-    Frame F = frame_layout(static_cast<char *>(frame), n);
+    Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list);
     const ShadeConst C = shade_const(sh, p);
     Layout LM = make_layout(M.n);
     const int ts = tile_shift_of(p);
@@ -465,7 +473,7 @@ int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays
     const int64_t n = rays->n;
     zero_gacc(G, st);
     if (n > 0) {
-        Frame F = frame_layout(static_cast<char *>(frame), n);
+        Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list);
         k_mesh_bwd_prep<<<grid_for(n), 256, 0, st>>>(F, n, grad);
         rs_rays rr[3];
         SetDesc S[3];
@@ -473,7 +481,14 @@ int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays
         rs_params ps = *p;
         ps.flags |= RS_PERSISTENT;
         int e;
-        if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
+        if (p->hit_list > 0) {
+            // stored lists of all three sets, then traversal for the rays whose list overflowed
+            if ((e = launch_sets(G, g, &ps, 3, S, true, st, true))) return e;
+            if (p->max_hits == 0 || p->max_hits > p->hit_list)
+                if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
+        } else {
+            if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
+        }
     }
     scatter_gacc(G, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;

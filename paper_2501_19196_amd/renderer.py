@@ -304,8 +304,10 @@ def trace_mesh(mbvh: BVH, rays: Rays, t_limit=None, any_hit=False):
     return t, tri
 
 
-def mesh_frame(n, device="cuda"):
-    return torch.empty(max(int(L.lib().rs_mesh_frame_bytes(int(n))), 256), dtype=torch.uint8, device=device)
+def mesh_frame(n, params=None, device="cuda"):
+    pc = params.c() if params is not None else None
+    nbytes = int(L.lib().rs_mesh_frame_bytes(int(n), C.byref(pc) if pc is not None else None))
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
 def render_mesh_fwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Shading, rays: Rays, params: Params,
@@ -314,7 +316,7 @@ def render_mesh_fwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Sha
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
     if frame is None:
-        frame = mesh_frame(n, rays.origin.device)
+        frame = mesh_frame(n, params, rays.origin.device)
     gc, mc, sc, rc, pc = g.c(), mesh.c(), shading.c(), rays.c(), params.c()
     L.check(L.lib().rs_render_mesh_fwd(C.byref(gbvh.desc), C.byref(mbvh.desc), C.byref(gc), C.byref(mc), C.byref(sc),
                                        C.byref(rc), C.byref(pc), _ptr(out), _ptr(frame), _stream()),

@@ -258,11 +258,14 @@ def test_mixed_forward_bare_mesh_lambert():
     _forward_parity(far, mesh, o, d, views, R.Params(bg=(0.25, 0.5, 0.75)), "bare")
 
 
-def test_mixed_gradients():
-    print("case mixed grads", flush=True)
+@pytest.mark.parametrize("hit_list", [0, 8, 256])
+def test_mixed_gradients(hit_list):
+    """Adjoint parity of the mixed render, recomputing or from stored lists
+    (a capacity of 8 overflows on many rays, which then re-traverse)."""
+    print("case mixed grads", hit_list, flush=True)
     G, R = _g()
     sc, mesh, o, d, views = _case(seed=7, n=2000, res=(32, 24))
-    p = R.Params(bg=(0.25, 0.5, 0.75))
+    p = R.Params(bg=(0.25, 0.5, 0.75), hit_list=hit_list)
     op = G.oracle_params(O, p)
     sh, fwd = _oracle_mixed(sc, mesh, o, d, op)
     edge, gauss = _ambiguity(sc, mesh, o, d, op, fwd)
