@@ -63,6 +63,7 @@ def lib():
         L.orc_ray_hits.restype = C.c_int64
         L.orc_render_fwd.argtypes = [P, P, P, P, P, P, C.c_int]
         L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, C.c_int]
+        L.orc_render_bwd_paper.argtypes = [P, P, P, C.c_double, P, P, P, P, P, P, P, P, C.c_int]
         L.orc_ray_dC_dalpha.argtypes = [P, P, C.c_int64, P, C.c_int64, P]
         L.orc_ray_dC_dalpha.restype = C.c_int64
         L.orc_ray_alternatives.argtypes = [P, P, C.c_int64, P, C.c_double, C.c_double, C.c_double, C.c_int,
@@ -146,6 +147,24 @@ def render_bwd(scene, origin, direction, grad_rgb, params=None, t_max=None, bg=N
     if want_bg:
         grads["bg"] = dbg
     return grads
+
+
+def render_bwd_paper(scene, origin, direction, grad_rgb, params=None, eps2=1e-4, t_max=None, bg=None, threads=0):
+    """The paper's backward variant with the second threshold eps2 (see
+    orc_render_bwd_paper). Returns (grads, extra[n] second-phase hits per ray,
+    near[n] rays with an eps2 decision within rounding)."""
+    params = params or Params()
+    b = _Bound(scene, origin, direction, t_max, bg)
+    n = scene.n
+    g = np.ascontiguousarray(grad_rgb, dtype=np.float64).reshape(-1, 3)
+    dm = np.zeros((n, 3)); ds = np.zeros((n, 3)); dq = np.zeros((n, 4)); do = np.zeros(n); dc = np.zeros((n, 3))
+    nr = b.o.shape[0]
+    extra = np.zeros(nr, np.int32)
+    near = np.zeros(nr, np.int32)
+    p = params.c()
+    lib().orc_render_bwd_paper(C.byref(b.sc), C.byref(b.rays), C.byref(p), float(eps2), _ptr(g), _ptr(dm),
+                               _ptr(ds), _ptr(dq), _ptr(do), _ptr(dc), _ptr(extra), _ptr(near), int(threads))
+    return dict(mean=dm, scale=ds, quat=dq, opacity=do, rgb=dc), extra, near.astype(bool)
 
 
 def ray_hits(scene, origin, direction, k, params=None, t_max=None, cap=1 << 16):

@@ -523,6 +523,102 @@ int orc_render_bwd(const orc_scene *sc, const orc_rays *r, const orc_params *p, 
 }
 
 /* ---------------------------------------------------------------------- */
+/* The paper's backward variant (Sec. 3 and Sec. 5, second threshold): when a
+ * ray stops because its transmittance fell below eps1 after L hits, the
+ * forward keeps collecting the next hits j = L+1, L+2, ... (without changing
+ * the image) while the transmittance of the collected ones,
+ * prod_{k=L+1}^{j-1} (1 - alpha_k), is not below eps2 and the buffer holds
+ * fewer than K_max entries. The gradient of the last "meaningful" Gaussian L
+ * then sees those hits instead of only the background. Reading: the
+ * gradients are those of
+ *   E = C_<=L + T_{L+1} R2,  R2 = sum_{j>L} c_j alpha_j prod_{L<k<j} (1 - alpha_k)
+ *                              + prod_{L<k<=J} (1 - alpha_k) bg,
+ * with the collected set frozen, for the composited Gaussians only; that is
+ * the exact adjoint with bg replaced by R2. extra[k] receives J - L and
+ * near[k] = 1 when some eps2 decision had |T2 - eps2| <= 1e-3 eps2. */
+static int64_t phase2(const orc_scene *sc, const orc_params *p, double eps2, const orc_hit *h, int64_t n,
+                      const double bg[3], double R2[3], int *near)
+{
+    double T = 1.0;
+    int64_t L = 0;
+    int by_eps = 0;
+    for (int64_t k = 0; k < n; ++k) {
+        if (p->max_hits > 0 && L >= p->max_hits) break;
+        T *= (1.0 - h[k].alpha);
+        ++L;
+        if (T < p->eps1) {
+            by_eps = 1;
+            break;
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch) R2[ch] = 0.0;
+    double T2 = 1.0;
+    int64_t x = 0;
+    *near = 0;
+    if (by_eps) {
+        for (int64_t j = L; j < n; ++j) {
+            if (p->max_hits > 0 && L + x >= p->max_hits) break;
+            if (fabs(T2 - eps2) <= 1e-3 * eps2) *near = 1;
+            if (T2 < eps2) break;
+            double c[3];
+            colour_of(sc, p, h[j].idx, c);
+            for (int ch = 0; ch < 3; ++ch) R2[ch] += T2 * h[j].alpha * c[ch];
+            T2 *= (1.0 - h[j].alpha);
+            ++x;
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch) R2[ch] += T2 * bg[ch];
+    return x;
+}
+
+int orc_render_bwd_paper(const orc_scene *sc, const orc_rays *r, const orc_params *p, double eps2,
+                         const double *grad_rgb, double *d_mean, double *d_scale, double *d_quat, double *d_opacity,
+                         double *d_rgb, int32_t *extra, int32_t *near, int nthreads)
+{
+    set_threads(nthreads);
+    memset(d_mean, 0, sizeof(double) * 3 * sc->n);
+    memset(d_scale, 0, sizeof(double) * 3 * sc->n);
+    memset(d_quat, 0, sizeof(double) * 4 * sc->n);
+    memset(d_opacity, 0, sizeof(double) * sc->n);
+    memset(d_rgb, 0, sizeof(double) * 3 * sc->n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < r->n; ++k) {
+        double o[3], d[3];
+        ray_of(r, k, o, d);
+        const double *g = grad_rgb + 3 * k;
+        orc_hit *h;
+        int64_t n = collect(sc, o, d, p, tmax_of(r, k), &h);
+        double R2[3];
+        int nr = 0;
+        int64_t x = phase2(sc, p, eps2, h, n, bg_of(r, p, k), R2, &nr);
+        if (extra) extra[k] = (int32_t)x;
+        if (near) near[k] = nr;
+        double *ga = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+        double *w = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+        int64_t L = adjoint_list(sc, p, h, n, R2, g, ga, w);
+        for (int64_t j = 0; j < L; ++j) {
+            int64_t i = h[j].idx;
+            if (!p->zero_colour)
+                for (int ch = 0; ch < 3; ++ch) atomic_add(&d_rgb[3 * i + ch], g[ch] * w[j]);
+            double e = exp(-0.5 * h[j].h2);
+            atomic_add(&d_opacity[i], ga[j] * e);
+            double g_h2 = ga[j] * (-0.5 * h[j].alpha);
+            orc_geom geo;
+            whiten(sc, i, o, d, &geo);
+            double dm[3], ds[3], dq[4];
+            dh2_dparams(sc, i, &geo, d, dm, ds, dq);
+            for (int c = 0; c < 3; ++c) atomic_add(&d_mean[3 * i + c], g_h2 * dm[c]);
+            for (int c = 0; c < 3; ++c) atomic_add(&d_scale[3 * i + c], g_h2 * ds[c]);
+            for (int c = 0; c < 4; ++c) atomic_add(&d_quat[4 * i + c], g_h2 * dq[c]);
+        }
+        free(ga);
+        free(w);
+        free(h);
+    }
+    return 0;
+}
+
+/* ---------------------------------------------------------------------- */
 /* Acceptance alternatives. A float32 renderer may legitimately differ from
  * this oracle where the decision depends on a quantity within its rounding
  * error: (i) membership when |h2 - Q| <= dh * Q, (ii) membership when
