@@ -535,7 +535,8 @@ int orc_render_bwd(const orc_scene *sc, const orc_rays *r, const orc_params *p, 
  *                              + prod_{L<k<=J} (1 - alpha_k) bg,
  * with the collected set frozen, for the composited Gaussians only; that is
  * the exact adjoint with bg replaced by R2. extra[k] receives J - L and
- * near[k] = 1 when some eps2 decision had |T2 - eps2| <= 1e-3 eps2. */
+ * near[k] = 1 when some eps2 decision on a rounded T2 (after at least one
+ * collected hit) had |T2 - eps2| <= 1e-3 eps2. */
 static int64_t phase2(const orc_scene *sc, const orc_params *p, double eps2, const orc_hit *h, int64_t n,
                       const double bg[3], double R2[3], int *near)
 {
@@ -558,7 +559,8 @@ static int64_t phase2(const orc_scene *sc, const orc_params *p, double eps2, con
     if (by_eps) {
         for (int64_t j = L; j < n; ++j) {
             if (p->max_hits > 0 && L + x >= p->max_hits) break;
-            if (fabs(T2 - eps2) <= 1e-3 * eps2) *near = 1;
+            /* before the first collected hit T2 is the exact empty product 1: no rounding */
+            if (x > 0 && fabs(T2 - eps2) <= 1e-3 * eps2) *near = 1;
             if (T2 < eps2) break;
             double c[3];
             colour_of(sc, p, h[j].idx, c);
