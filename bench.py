@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
     ap.add_argument("--hit-list", type=int, default=512,
                     help="stored hit-list capacity per ray (0 = the adjoint re-traverses the BVH)")
+    ap.add_argument("--paper-gradient", action="store_true",
+                    help="the paper's backward variant (second threshold eps2 = --eps2); needs --hit-list >= 512")
+    ap.add_argument("--eps2", type=float, default=1e-4)
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -91,8 +94,9 @@ def main():
     rays = R.Rays(t(o), t(d), views=views)
     fixed = args.kbuf or args.persistent or args.tile_width
     # the mesh render keeps lists for its three ray sets in the frame: capacity capped at 256
-    base = R.Params(kbuf=args.kbuf, flags=2 if args.persistent else 0, tile_width=args.tile_width,
-                    hit_list=args.hit_list if mesh_np is None else min(args.hit_list, 256))
+    base = R.Params(kbuf=args.kbuf, flags=(2 if args.persistent else 0) | (16 if args.paper_gradient else 0),
+                    tile_width=args.tile_width, hit_list=args.hit_list if mesh_np is None else min(args.hit_list, 256),
+                    eps2=args.eps2)
     nr = o.shape[0]
     n = sc.n
 
@@ -362,6 +366,7 @@ def main():
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
                    "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
                    "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None, "hit_list": base.hit_list,
+                   "gradient": f"paper (eps2 {args.eps2:g})" if args.paper_gradient else "exact",
                    "launch_fwd": dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2),
                                       tile_width=pf.tile_width or 8),
                    "launch_bwd": dict(kbuf=pb.kbuf or 24, persistent=bool(pb.flags & 2),

@@ -63,6 +63,12 @@ enum {
                                       (transmittance / shadow rays) */
 #define RS_COUNTERS     (1u << 3)  /* count traversal work (see rs_read_counters; not with
                                       RS_BRUTE_FORCE); an instrumented kernel variant */
+#define RS_PAPER_GRADIENT (1u << 4) /* the paper's backward variant (Sec. 3, Sec. 5): after an
+                                      eps1 stop the forward keeps the ids of the next hits
+                                      while their transmittance stays >= eps2 (image unchanged),
+                                      and the last composited Gaussian's gradient sees them
+                                      instead of the background. Needs 0 < max_hits <= hit_list.
+                                      Not for the mesh renders. */
 
 #define RS_MAX_VIEWS 64
 
@@ -119,6 +125,7 @@ typedef struct {
     int32_t stack_depth;
     int32_t tile_width;
     int32_t hit_list;
+    float eps2;  /* second threshold of RS_PAPER_GRADIENT, in [0, 1] */
 } rs_params;
 
 /* Gradient outputs (device, float32, same shapes as the inputs). Any pointer
@@ -134,7 +141,7 @@ typedef struct {
 
 /* Fill *p with the defaults: Q = 11.3449 (chi^2(3) 0.99 quantile), eps1 = 1e-4,
  * t_min = 0, max_hits = 512, black background, no flags, automatic kbuf,
- * stack depth and packet size. */
+ * stack depth and packet size, no hit lists, eps2 = 1e-4. */
 void rs_default_params(rs_params *p);
 
 /* Device workspace needed to build and keep a BVH over n Gaussians. */

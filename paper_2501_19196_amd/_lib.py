@@ -23,6 +23,7 @@ RS_BRUTE_FORCE = 1 << 0
 RS_PERSISTENT = 1 << 1
 RS_ZERO_COLOUR = 1 << 2
 RS_COUNTERS = 1 << 3
+RS_PAPER_GRADIENT = 1 << 4
 RS_MAX_VIEWS = 64
 
 # Every symbol include/raysplats.h declares.
@@ -50,7 +51,7 @@ class rs_rays(C.Structure):
 class rs_params(C.Structure):
     _fields_ = [("Q", C.c_float), ("eps1", C.c_float), ("t_min", C.c_float), ("max_hits", C.c_int32),
                 ("bg", C.c_float * 3), ("flags", C.c_uint32), ("kbuf", C.c_int32), ("stack_depth", C.c_int32),
-                ("tile_width", C.c_int32), ("hit_list", C.c_int32)]
+                ("tile_width", C.c_int32), ("hit_list", C.c_int32), ("eps2", C.c_float)]
 
 
 class rs_grads(C.Structure):

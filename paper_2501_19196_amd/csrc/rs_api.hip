@@ -25,8 +25,14 @@ static int check_params(const rs_params *p)
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
     if (p->tile_width != 0 && p->tile_width != 4 && p->tile_width != 8 && p->tile_width != 16 && p->tile_width != 32)
         return RS_ERR_INVALID_ARG;
-    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS)) return RS_ERR_INVALID_ARG;
+    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS | RS_PAPER_GRADIENT))
+        return RS_ERR_INVALID_ARG;
     if (p->hit_list < 0 || p->hit_list > 4096) return RS_ERR_INVALID_ARG;
+    if (p->flags & RS_PAPER_GRADIENT) {
+        // the second phase lives in the stored lists, which must never overflow
+        if (!(p->eps2 >= 0.0f && p->eps2 <= 1.0f)) return RS_ERR_INVALID_ARG;
+        if (p->max_hits <= 0 || p->hit_list < p->max_hits) return RS_ERR_INVALID_ARG;
+    }
     return RS_OK;
 }
 
@@ -68,6 +74,7 @@ void rs_default_params(rs_params *p)
     p->eps1 = 1e-4f;
     p->t_min = 0.0f;
     p->max_hits = 512;
+    p->eps2 = 1e-4f;
 }
 
 size_t rs_bvh_workspace_bytes(int64_t n_gaussians)
@@ -221,7 +228,7 @@ int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
     if ((e = check_rays(rays))) return e;
     if ((e = check_mesh(m))) return e;
     if ((e = check_shading(sh))) return e;
-    if (rays->t_max || rays->bg) return RS_ERR_UNSUPPORTED;
+    if (rays->t_max || rays->bg || (p->flags & RS_PAPER_GRADIENT)) return RS_ERR_UNSUPPORTED;
     BvhDesc G, M;
     if ((e = check_bvh(gauss_bvh, g, p, G))) return e;
     if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
@@ -239,7 +246,7 @@ int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
     if ((e = check_rays(rays))) return e;
     if ((e = check_mesh(m))) return e;
     if ((e = check_shading(sh))) return e;
-    if (rays->t_max || rays->bg) return RS_ERR_UNSUPPORTED;
+    if (rays->t_max || rays->bg || (p->flags & RS_PAPER_GRADIENT)) return RS_ERR_UNSUPPORTED;
     BvhDesc G, M;
     if ((e = check_bvh(gauss_bvh, g, p, G))) return e;
     if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;

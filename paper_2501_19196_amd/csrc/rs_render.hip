@@ -45,6 +45,8 @@ struct RenderParams {
     int32_t tile_shift;
     int32_t strip_tiles;   // persistent: tile strip width of the packet order (0 = row-major)
     int32_t hit_cap;       // stored hit-list capacity per ray (0 = none)
+    int32_t paper;         // RS_PAPER_GRADIENT: second phase after an eps1 stop
+    float eps2;
     int64_t chunk;         // persistent: packets per XCD queue
     ViewEntry views[RS_MAX_VIEWS];
 };
@@ -386,6 +388,21 @@ struct HitData {
     float al, cr, cg, cb, Tk;
 };
 
+// alpha of Gaussian gid along the ray, with the leaf test's own arithmetic
+__device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
+                                  const int32_t *__restrict__ inv, float Q, float4 &r0, float4 &r1, float4 &r2,
+                                  float4 &r3)
+{
+    const int32_t js = inv[gid];
+    r0 = records[4 * js + 0];
+    r1 = records[4 * js + 1];
+    r2 = records[4 * js + 2];
+    r3 = records[4 * js + 3];
+    float t1, h2;
+    ellipsoid_hit(ray, r0, r1, r2, r3, Q, t1, h2);
+    return r3.w * __expf(-0.5f * h2);
+}
+
 __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
                                      const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
                                      const RenderParams &P, Accum &A, HitData &H)
@@ -393,14 +410,7 @@ __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, con
     H.al = H.cr = H.cg = H.cb = 0.0f;
     H.Tk = A.T;
     if (act) {
-        const int32_t js = inv[gid];
-        H.r0 = records[4 * js + 0];
-        H.r1 = records[4 * js + 1];
-        H.r2 = records[4 * js + 2];
-        H.r3 = records[4 * js + 3];
-        float t1, h2;
-        ellipsoid_hit(ray, H.r0, H.r1, H.r2, H.r3, P.Q, t1, h2);
-        H.al = H.r3.w * __expf(-0.5f * h2);
+        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3);
         if (!zc) {
             H.cr = rgb[3 * gid];
             H.cg = rgb[3 * gid + 1];
@@ -574,6 +584,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         bool live = valid && P.n_gauss > 0 && tmax > P.t_min;
         double last = -kNoHit;  // keys of this round must exceed it
         LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        // RS_PAPER_GRADIENT forward: after an eps1 stop the lane keeps consuming hits without
+        // compositing them, recording their ids while T2 (their transmittance) stays >= eps2
+        const bool paper = !BWD && P.paper && S.ids;
+        bool phase2 = false;
+        float T2 = 1.0f;
+        int32_t extra = 0;
         if (BWD && valid) {
             Gd.gr = S.grad[3 * ray_id];
             Gd.gg = S.grad[3 * ray_id + 1];
@@ -671,10 +687,29 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 if (COUNT) c_lcomp += __popcll(act_mask);
                 const uint32_t gid = hit_key_gid(key_s);
                 HitData H;
+                if (paper && phase2) {
+                    if (act) {
+                        const int32_t slot = A.n + extra;
+                        if (T2 < P.eps2 || slot >= P.max_hits) {
+                            live = false;  // the second phase ends before this hit
+                        } else {
+                            float4 r0, r1, r2, r3;
+                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3);
+                            S.ids[int64_t(slot) * P.n_rays + ray_id] = int32_t(gid);
+                            T2 *= 1.0f - al;
+                            ++extra;
+                        }
+                    }
+                    continue;
+                }
                 composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
                 if (!BWD && act && S.ids && A.n <= P.hit_cap)
                     S.ids[int64_t(A.n - 1) * P.n_rays + ray_id] = int32_t(gid);
                 const bool stopped = act && stop_after(A, P);
+                if (paper && stopped && A.T < P.eps1) {
+                    phase2 = true;  // stays live for the second phase
+                    continue;
+                }
                 if (BWD)
                     adjoint_hit<COUNT>(act, act_mask, stopped, gid, ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
                                        lane, c_group);
@@ -692,7 +727,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             if (S.state) S.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
                                                            __builtin_fmaf(A.T, bgg, A.Cg),
                                                            __builtin_fmaf(A.T, bgb, A.Cb), A.T);
-            if (S.count) S.count[ray_id] = A.n;
+            if (S.count) S.count[ray_id] = A.n | (extra << 16);
         }
     }
     if (COUNT && lane == 0 && c_pkt > 0) {
@@ -729,10 +764,13 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
         const LaneRay LR = lane_ray(P, ptr, pkt, lane);
         const RaySet &S = ptr.set[LR.si];
         const bool zc = S.zero_colour != 0;
-        int32_t cnt = 0;
+        int32_t cnt = 0, extra = 0;
+        float Tfin = 1.0f;
         LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (LR.valid) {
-            cnt = S.count[LR.id];
+            const int32_t packed = S.count[LR.id];
+            cnt = packed & 0xffff;
+            extra = packed >> 16;
             Gd.gr = S.grad[3 * LR.id];
             Gd.gg = S.grad[3 * LR.id + 1];
             Gd.gb = S.grad[3 * LR.id + 2];
@@ -740,9 +778,42 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
             Gd.Cor = st.x;
             Gd.Cog = st.y;
             Gd.Cob = st.z;
+            Tfin = st.w;
         }
         const bool live = LR.valid && cnt > 0 && cnt <= P.hit_cap && P.n_gauss > 0 &&
                           !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
+        // RS_PAPER_GRADIENT: the colour R2 behind the last composited hit is that of the
+        // second-phase hits (then the background) instead of the background alone; the
+        // final colour the adjoint differentiates becomes C_<=L + T_{L+1} R2
+        float bgr = LR.bgr, bgg = LR.bgg, bgb = LR.bgb;
+        if (P.paper) {
+            float R2r = 0.0f, R2g = 0.0f, R2b = 0.0f, T2 = 1.0f;
+            for (int32_t k = 0;; ++k) {
+                const bool a2 = live && k < extra;
+                if (!wave_ballot(a2)) break;
+                if (a2) {
+                    const uint32_t gid = uint32_t(S.ids[int64_t(cnt + k) * P.n_rays + LR.id]);
+                    float4 r0, r1, r2, r3;
+                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3);
+                    if (!zc) {
+                        const float w = T2 * al;
+                        R2r = __builtin_fmaf(w, ptr.rgb[3 * gid], R2r);
+                        R2g = __builtin_fmaf(w, ptr.rgb[3 * gid + 1], R2g);
+                        R2b = __builtin_fmaf(w, ptr.rgb[3 * gid + 2], R2b);
+                    }
+                    T2 *= 1.0f - al;
+                }
+            }
+            R2r = __builtin_fmaf(T2, bgr, R2r);
+            R2g = __builtin_fmaf(T2, bgg, R2g);
+            R2b = __builtin_fmaf(T2, bgb, R2b);
+            Gd.Cor += Tfin * (R2r - bgr);
+            Gd.Cog += Tfin * (R2g - bgg);
+            Gd.Cob += Tfin * (R2b - bgb);
+            bgr = R2r;
+            bgg = R2g;
+            bgb = R2b;
+        }
         Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
         for (int32_t k = 0;; ++k) {
             const bool act = live && k < cnt;
@@ -753,8 +824,8 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
             HitData H;
             composite_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P, A, H);
             const bool stopped = act && stop_after(A, P);
-            adjoint_hit<COUNT>(act, act_mask, stopped, gid, LR.ray, H, A, Gd, LR.bgr, LR.bgg, LR.bgb, zc, ptr.quat,
-                               ptr.gacc, lane, c_group);
+            adjoint_hit<COUNT>(act, act_mask, stopped, gid, LR.ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
+                               lane, c_group);
         }
     }
     if (COUNT && lane == 0 && c_pkt > 0) {
@@ -877,6 +948,8 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     P.n_packets = packets * nsets;
     P.strip_tiles = kStripTiles;
     P.hit_cap = sets[0].count ? p->hit_list : 0;
+    P.paper = (p->flags & RS_PAPER_GRADIENT) && sets[0].count ? 1 : 0;
+    P.eps2 = p->eps2;
     P.chunk = (P.n_packets + kXcdQueues - 1) / kXcdQueues;
 
     Ptrs ptr{};

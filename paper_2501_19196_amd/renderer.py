@@ -27,6 +27,7 @@ class Params:
     stack_depth: int = 0
     tile_width: int = 0
     hit_list: int = 0
+    eps2: float = 1e-4
 
     def c(self):
         p = L.rs_params()
@@ -38,6 +39,7 @@ class Params:
         p.stack_depth = int(self.stack_depth)
         p.tile_width = int(self.tile_width)
         p.hit_list = int(self.hit_list)
+        p.eps2 = float(self.eps2)
         return p
 
 
@@ -183,7 +185,7 @@ def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, sta
 def _params_from_c(cp, like):
     return Params(Q=like.Q, eps1=like.eps1, t_min=like.t_min, max_hits=like.max_hits, bg=tuple(like.bg),
                   flags=int(cp.flags), kbuf=int(cp.kbuf), stack_depth=int(cp.stack_depth),
-                  tile_width=int(cp.tile_width), hit_list=int(cp.hit_list))
+                  tile_width=int(cp.tile_width), hit_list=int(cp.hit_list), eps2=like.eps2)
 
 
 def autotune(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb=None, reps=2):

@@ -102,6 +102,12 @@ def test_invalid_arguments_are_rejected(L):
         lib.rs_default_params(C.byref(q))
         setattr(q, field, val)
         assert lib.rs_build_bvh(C.byref(g), C.byref(q), fake, 1 << 30, C.byref(out), None) == L.RS_ERR_INVALID_ARG
+    # the paper's gradient variant needs lists that cannot overflow and eps2 in [0, 1]
+    for hit_list, max_hits, eps2 in ((0, 512, 1e-4), (256, 512, 1e-4), (512, 0, 1e-4), (512, 512, 2.0)):
+        q = L.rs_params()
+        lib.rs_default_params(C.byref(q))
+        q.flags, q.hit_list, q.max_hits, q.eps2 = L.RS_PAPER_GRADIENT, hit_list, max_hits, eps2
+        assert lib.rs_build_bvh(C.byref(g), C.byref(q), fake, 1 << 30, C.byref(out), None) == L.RS_ERR_INVALID_ARG
     # an uninitialised descriptor is rejected by the render calls
     r = L.rs_rays(4, fake, fake, None, None, 0, None)
     assert lib.rs_render_fwd(C.byref(L.rs_bvh()), C.byref(g), C.byref(r), C.byref(p), fake, None, None) == \
