@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--paper-gradient", action="store_true",
                     help="the paper's backward variant (second threshold eps2 = --eps2); needs --hit-list >= 512")
     ap.add_argument("--eps2", type=float, default=1e-4)
+    ap.add_argument("--loss", choices=("l1", "paper"), default="l1",
+                    help="l1: mean L1 (gradient by torch); paper: (1 - 0.2) L2 + 0.2 D-SSIM per view (rs_loss)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -150,6 +152,17 @@ def main():
         log("autotune", tune)
 
     kt = {"build": [], "fwd": [], "bwd": []}
+    lws = [R.loss_workspace(vw, vh, dev) for _, vw, vh in views] if args.loss == "paper" else None
+    lval = torch.empty(max(len(views), 1), dtype=torch.float32, device=dev)
+    lgrad = torch.empty((nr, 3), dtype=torch.float32, device=dev)
+
+    def loss_grad():
+        if args.loss == "l1":
+            return torch.sign(out - target) * (1.0 / (3.0 * nr))  # d/dout of mean L1
+        for k, (off, vw, vh) in enumerate(views):  # the paper's loss, one launch set per view
+            sl = slice(off, off + vw * vh)
+            R.image_loss(out[sl], target[sl], vw, vh, 0.2, ws=lws[k], out=lval[k:k + 1], grad_out=lgrad[sl])
+        return lgrad
 
     def step(record=False):
         e = [ev() for _ in range(5)] if record else None
@@ -161,7 +174,7 @@ def main():
         render(bvh, g, pf, out, state)
         if record:
             e[2].record()
-        grad = torch.sign(out - target) * (1.0 / (3.0 * nr))  # d/dout of mean L1
+        grad = loss_grad()
         if record:
             e[3].record()
         adjoint(bvh, pb, grad, state)
@@ -367,6 +380,7 @@ def main():
                    "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
                    "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None, "hit_list": base.hit_list,
                    "gradient": f"paper (eps2 {args.eps2:g})" if args.paper_gradient else "exact",
+                   "loss": "mean L1" if args.loss == "l1" else "0.8 L2 + 0.2 D-SSIM (11x11, sigma 1.5)",
                    "launch_fwd": dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2),
                                       tile_width=pf.tile_width or 8),
                    "launch_bwd": dict(kbuf=pb.kbuf or 24, persistent=bool(pb.flags & 2),

@@ -292,6 +292,37 @@ int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
                        const rs_shading *sh, const rs_rays *rays, const rs_params *p, const float *grad_rgb,
                        void *frame, rs_grads *out, void *stream);
 
+/* --------------------------------------------------------- training loss */
+/* The paper's training loss (Sec. 3, loss function) of one image against its
+ * target, and its gradient (App. A.7). Per colour channel
+ *   L_ch = (1 - lambda) mean (I - I^)^2 + lambda (1 - mean SSIM) / 2,
+ * and L is the mean over the three channels. SSIM uses the moments of a
+ * normalised Gaussian window (zero outside the image) with c1 = 0.01^2,
+ * c2 = 0.03^2 for intensities in [0, 1]; the gradient of mean SSIM is
+ * App. A.7's (1/hw) ((E * w) + I^ (F * w) - I (G * w)). The paper gives no
+ * window or lambda: the defaults are the usual 11 x 11 window (radius 5,
+ * sigma 1.5) and lambda = 0.2. */
+typedef struct {
+    float lambda;   /* D-SSIM weight in [0, 1] */
+    int32_t radius; /* window radius, 1..7 */
+    float sigma;    /* window standard deviation, > 0 */
+} rs_loss_params;
+
+void rs_default_loss_params(rs_loss_params *lp);
+
+/* Device workspace of rs_loss for a width x height image (E, F, G maps and
+ * per-tile partial sums), 256-byte aligned. */
+size_t rs_loss_workspace_bytes(int32_t width, int32_t height);
+
+/* img, target: device float32 [height][width][3] (row-major pixels, the
+ * order of a view's rays). loss: device float32 [1], written. grad: device
+ * float32 [height][width][3], written with dL/dimg (NULL: loss only).
+ * ws: rs_loss_workspace_bytes(width, height) bytes, 256-byte aligned.
+ * Asynchronous on `stream`; errors for null pointers, empty images or bad
+ * knobs are returned before anything is enqueued. */
+int rs_loss(const float *img, const float *target, int32_t width, int32_t height, const rs_loss_params *lp,
+            float *loss, float *grad, void *ws, void *stream);
+
 /* Human-readable text of a status code (static string). */
 const char *rs_status_string(int code);
 

@@ -30,7 +30,7 @@ RS_MAX_VIEWS = 64
 EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", "rs_build_bvh", "rs_render_fwd",
            "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download",
            "rs_default_shading", "rs_build_mesh_bvh", "rs_trace_mesh", "rs_mesh_frame_bytes", "rs_render_mesh_fwd",
-           "rs_render_mesh_bwd", "rs_autotune")
+           "rs_render_mesh_bwd", "rs_autotune", "rs_default_loss_params", "rs_loss_workspace_bytes", "rs_loss")
 RS_TUNE_MAX = 32
 
 
@@ -77,6 +77,10 @@ class rs_tune(C.Structure):
     _fields_ = [("fwd", rs_params), ("bwd", rs_params), ("n", C.c_int32), ("kbuf", C.c_int32 * RS_TUNE_MAX),
                 ("persistent", C.c_int32 * RS_TUNE_MAX), ("tile_width", C.c_int32 * RS_TUNE_MAX),
                 ("ms_fwd", C.c_float * RS_TUNE_MAX), ("ms_bwd", C.c_float * RS_TUNE_MAX)]
+
+
+class rs_loss_params(C.Structure):
+    _fields_ = [("lambda_", C.c_float), ("radius", C.c_int32), ("sigma", C.c_float)]
 
 
 class RaySplatsError(RuntimeError):
@@ -136,6 +140,12 @@ def lib():
     L.rs_autotune.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_rays), C.POINTER(rs_params), P,
                               P, P, C.POINTER(rs_grads), C.c_int, C.POINTER(rs_tune), P]
     L.rs_autotune.restype = C.c_int
+    L.rs_default_loss_params.argtypes = [C.POINTER(rs_loss_params)]
+    L.rs_default_loss_params.restype = None
+    L.rs_loss_workspace_bytes.argtypes = [C.c_int32, C.c_int32]
+    L.rs_loss_workspace_bytes.restype = C.c_size_t
+    L.rs_loss.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(rs_loss_params), P, P, P, P]
+    L.rs_loss.restype = C.c_int
     _lib = L
     return L
 

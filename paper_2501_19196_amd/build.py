@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librs.so")
-SOURCES = ["rs_api.hip", "rs_build.hip", "rs_render.hip", "rs_mesh.hip"]
+SOURCES = ["rs_api.hip", "rs_build.hip", "rs_render.hip", "rs_mesh.hip", "rs_loss.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

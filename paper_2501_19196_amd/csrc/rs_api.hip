@@ -357,6 +357,30 @@ int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, c
     return e;
 }
 
+void rs_default_loss_params(rs_loss_params *lp)
+{
+    if (!lp) return;
+    lp->lambda = 0.2f;
+    lp->radius = 5;
+    lp->sigma = 1.5f;
+}
+
+size_t rs_loss_workspace_bytes(int32_t width, int32_t height)
+{
+    return (width > 0 && height > 0) ? loss_workspace_bytes(width, height) : 0;
+}
+
+int rs_loss(const float *img, const float *target, int32_t width, int32_t height, const rs_loss_params *lp,
+            float *loss, float *grad, void *ws, void *stream)
+{
+    if (!img || !target || !lp || !loss || !ws || width <= 0 || height <= 0) return RS_ERR_INVALID_ARG;
+    if (!(lp->lambda >= 0.0f && lp->lambda <= 1.0f) || lp->radius < 1 || lp->radius > 7 || !(lp->sigma > 0.0f))
+        return RS_ERR_INVALID_ARG;
+    if (int64_t(width) * height > (int64_t(1) << 30)) return RS_ERR_UNSUPPORTED;
+    if (!aligned(ws, 256)) return RS_ERR_INVALID_ARG;
+    return launch_loss(img, target, width, height, lp, loss, grad, ws, static_cast<hipStream_t>(stream));
+}
+
 const char *rs_status_string(int code)
 {
     switch (code) {

@@ -340,6 +340,45 @@ def render_mesh_bwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Sha
     return grads
 
 
+# ------------------------------------------------------------ training loss
+
+def loss_workspace(width, height, device="cuda"):
+    return torch.empty(max(int(L.lib().rs_loss_workspace_bytes(int(width), int(height))), 256), dtype=torch.uint8,
+                       device=device)
+
+
+def image_loss(img, target, width, height, lam=0.2, radius=5, sigma=1.5, grad=True, ws=None, out=None,
+               grad_out=None):
+    """(1 - lam) L2 + lam D-SSIM of one image ([height*width, 3] or [height, width, 3])
+    against its target (rs_loss). Returns (loss[1], grad or None)."""
+    img = _dev(img.contiguous(), "img")
+    target = _dev(target.contiguous(), "target")
+    lp = L.rs_loss_params(float(lam), int(radius), float(sigma))
+    ws = ws if ws is not None else loss_workspace(width, height, img.device)
+    loss = out if out is not None else torch.empty(1, dtype=torch.float32, device=img.device)
+    g = (_dev(grad_out, "grad_out") if grad_out is not None else torch.empty_like(img)) if grad else None
+    L.check(L.lib().rs_loss(_ptr(img), _ptr(target), int(width), int(height), C.byref(lp), _ptr(loss), _ptr(g),
+                            _ptr(ws), _stream()), "rs_loss")
+    return loss, g
+
+
+class ImageLoss(torch.autograd.Function):
+    """Scalar (1 - lam) L2 + lam D-SSIM of one image against its target
+    (rs_loss); the gradient comes from the same launch."""
+
+    @staticmethod
+    def forward(ctx, img, target, width, height, lam=0.2, radius=5, sigma=1.5):
+        loss, g = image_loss(img.detach(), target.detach(), width, height, lam, radius, sigma,
+                             grad=img.requires_grad)
+        ctx.save_for_backward(g if g is not None else img.new_zeros(0))
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (g,) = ctx.saved_tensors
+        return (g * grad_out if g.numel() else None), None, None, None, None, None, None
+
+
 class MeshRender(torch.autograd.Function):
     """Gaussians + triangle mesh with mirror reflections and shadows; the
     Gaussian BVH is rebuilt every forward, the mesh BVH is given."""
@@ -364,7 +403,8 @@ class MeshRender(torch.autograd.Function):
 class RaySplatsRender(torch.autograd.Function):
     """rgb = render(mean, scale, quat, opacity, rgb; rays). The BVH is rebuilt
     in every forward (the parameters change every optimisation step); the
-    backward re-traverses the rays (no per-ray hit lists are stored)."""
+    backward replays the stored hit lists (params.hit_list > 0) or
+    re-traverses the rays."""
 
     @staticmethod
     def forward(ctx, mean, scale, quat, opacity, rgb, origin, direction, params, views):

@@ -36,13 +36,14 @@ def test_struct_layouts_match_header(L, tmp_path):
     """Every ctypes struct of the binding has the C compiler's size and field
     offsets for the header's struct (a small C program reads them)."""
     structs = [L.rs_gaussians, L.rs_view, L.rs_rays, L.rs_params, L.rs_grads, L.rs_bvh, L.rs_mesh, L.rs_shading,
-               L.rs_tune]
+               L.rs_tune, L.rs_loss_params]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "raysplats.h"', "int main(void) {"]
     for st in structs:
         name = st.__name__
         lines.append(f'printf("{name} size %zu\\n", sizeof({name}));')
         for f in st._fields_:
-            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0]}));')
+            # a trailing underscore marks a C name that is a Python keyword
+            lines.append(f'printf("{name} {f[0]} %zu\\n", offsetof({name}, {f[0].rstrip("_")}));')
     lines.append("return 0; }")
     src = tmp_path / "layout.c"
     src.write_text("\n".join(lines))
