@@ -74,6 +74,11 @@ def lib():
         L.orc_morton_codes.argtypes = [C.c_int64, P, P, P, P]
         L.orc_sort_codes.argtypes = [C.c_int64, P, P, P]
         L.orc_radix_tree.argtypes = [C.c_int64, P, P, P]
+        L.orc_leaf_boxes.argtypes = [C.c_int64, P, P, P, C.c_double, P, P]
+        L.orc_ploc.argtypes = [C.c_int64, P, P, P]
+        L.orc_ploc.restype = C.c_int64
+        L.orc_ploc_cap.argtypes = [C.c_int64]
+        L.orc_ploc_cap.restype = C.c_int64
         L.orc_mesh_closest.argtypes = [C.c_int64, P, P, C.c_int64, P, P, C.c_double, P, P, C.c_double, P]
         _lib = L
     return _lib
@@ -296,6 +301,33 @@ def radix_tree(sorted_codes):
     child = np.zeros((max(m, 1), 2), np.int32); leaf = np.zeros((max(m, 1), 2), np.int32)
     lib().orc_radix_tree(n, _ptr(s), _ptr(child), _ptr(leaf))
     return child[:m], leaf[:m].astype(bool)
+
+
+def leaf_boxes(mean, scale, quat, perm, Q=Q_DEFAULT):
+    """Bit-exact leaf boxes [n, 6] (lo xyz, hi xyz) in sorted order (row j: Gaussian perm[j])."""
+    m = np.ascontiguousarray(mean, np.float32)
+    s = np.ascontiguousarray(scale, np.float32)
+    q = np.ascontiguousarray(quat, np.float32)
+    pm = np.ascontiguousarray(perm, np.int32)
+    n = m.shape[0]
+    out = np.zeros((max(n, 1), 6), np.float32)
+    lib().orc_leaf_boxes(n, _ptr(m), _ptr(s), _ptr(q), float(Q), _ptr(pm), _ptr(out))
+    return out[:n]
+
+
+def ploc(leaf_boxes):
+    """PLOC tree over sorted leaf boxes: (child[n-1, 2] refs (< 0: leaf ~j), boxes[n-1, 2, 6], iterations)."""
+    lb = np.ascontiguousarray(leaf_boxes, np.float32)
+    n = lb.shape[0]
+    m = max(n - 1, 1)
+    child = np.zeros((m, 2), np.int32)
+    boxes = np.zeros((m, 2, 6), np.float32)
+    it = lib().orc_ploc(n, _ptr(lb), _ptr(child), _ptr(boxes))
+    return child[:max(n - 1, 0)], boxes[:max(n - 1, 0)], int(it)
+
+
+def ploc_cap(n):
+    return int(lib().orc_ploc_cap(int(n)))
 
 
 def mesh_closest(verts, tris, origin, direction, t_eps=1e-9, edge=0.0, want_amb=False):
