@@ -74,7 +74,7 @@ def lib():
         L.orc_morton_codes.argtypes = [C.c_int64, P, P, P, P]
         L.orc_sort_codes.argtypes = [C.c_int64, P, P, P]
         L.orc_radix_tree.argtypes = [C.c_int64, P, P, P]
-        L.orc_leaf_boxes.argtypes = [C.c_int64, P, P, P, C.c_double, P, P]
+        L.orc_leaf_boxes.argtypes = [C.c_int64, P, P, P, C.c_float, P, P]
         L.orc_ploc.argtypes = [C.c_int64, P, P, P]
         L.orc_ploc.restype = C.c_int64
         L.orc_ploc_cap.argtypes = [C.c_int64]

@@ -141,7 +141,8 @@ void orc_radix_tree(int64_t n, const uint32_t *sorted, int32_t *child, int32_t *
  *   e2_k = ((R_k0 s_0)^2 + (R_k1 s_1)^2) + (R_k2 s_2)^2   (half extent^2 / Q along axis k)
  *   e_k = sqrt(Q e2_k) (1 + 1e-5) + 1e-7 (1 + |m_k|)        (relative and absolute padding)
  *   box_k = [m_k - e_k rounded down to float32, m_k + e_k rounded up to float32]
- * Boxes are written in sorted order: row j is Gaussian perm[j].
+ * Q is the float32 knob of the render parameters, widened to FP64. Boxes are
+ * written in sorted order: row j is Gaussian perm[j].
  */
 static float f32_down(double x)
 {
@@ -157,7 +158,7 @@ static float f32_up(double x)
     return f;
 }
 
-void orc_leaf_boxes(int64_t n, const float *mean, const float *scale, const float *quat, double Q,
+void orc_leaf_boxes(int64_t n, const float *mean, const float *scale, const float *quat, float Q,
                     const int32_t *perm, float *boxes)
 {
     for (int64_t j = 0; j < n; ++j) {

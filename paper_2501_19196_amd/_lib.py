@@ -24,6 +24,7 @@ RS_PERSISTENT = 1 << 1
 RS_ZERO_COLOUR = 1 << 2
 RS_COUNTERS = 1 << 3
 RS_PAPER_GRADIENT = 1 << 4
+RS_BUILD_LBVH = 1 << 5
 RS_MAX_VIEWS = 64
 
 # Every symbol include/raysplats.h declares.

@@ -25,7 +25,7 @@ static int check_params(const rs_params *p)
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
     if (p->tile_width != 0 && p->tile_width != 4 && p->tile_width != 8 && p->tile_width != 16 && p->tile_width != 32)
         return RS_ERR_INVALID_ARG;
-    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS | RS_PAPER_GRADIENT))
+    if (p->flags & ~(RS_BRUTE_FORCE | RS_PERSISTENT | RS_ZERO_COLOUR | RS_COUNTERS | RS_PAPER_GRADIENT | RS_BUILD_LBVH))
         return RS_ERR_INVALID_ARG;
     if (p->hit_list < 0 || p->hit_list > 4096) return RS_ERR_INVALID_ARG;
     if (p->flags & RS_PAPER_GRADIENT) {
@@ -95,7 +95,7 @@ int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_
     if ((e = check_params(p))) return e;
     if (!ws || !out || !aligned(ws, 256)) return RS_ERR_INVALID_ARG;
     if (ws_bytes < make_layout(g->n).total) return RS_ERR_WORKSPACE;
-    e = launch_build(g, p->Q, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
+    e = launch_build(g, p->Q, (p->flags & RS_BUILD_LBVH) != 0, static_cast<char *>(ws), static_cast<hipStream_t>(stream));
     if (e) return e;
     BvhDesc D{};
     D.magic = kMagic;

@@ -245,24 +245,31 @@ __global__ __launch_bounds__(256) void k_records(const uint32_t *__restrict__ pe
     int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= n) return;
     uint32_t i = perm[j];
+    // Every FP64 step is one correctly rounded operation in the order written
+    // (explicit intrinsics, no contraction): the leaf boxes are bit-exact.
     double a = quat[4 * i], b = quat[4 * i + 1], c = quat[4 * i + 2], d = quat[4 * i + 3];
-    double nq = a * a + b * b + c * c + d * d;
+    double aa = __dmul_rn(a, a), bb = __dmul_rn(b, b), cc = __dmul_rn(c, c), dd = __dmul_rn(d, d);
+    double nq = __dadd_rn(__dadd_rn(__dadd_rn(aa, bb), cc), dd);
     if (!(nq > 0.0)) {
         a = 1.0;
         b = c = d = 0.0;
+        aa = 1.0;
+        bb = cc = dd = 0.0;
         nq = 1.0;
     }
-    double s = 2.0 / nq;
+    const double s = __ddiv_rn(2.0, nq);
+    const double ab = __dmul_rn(a, b), ac = __dmul_rn(a, c), ad = __dmul_rn(a, d), bc = __dmul_rn(b, c),
+                 bd = __dmul_rn(b, d), cd = __dmul_rn(c, d);
     double R[3][3];
-    R[0][0] = 1.0 - s * (c * c + d * d);
-    R[0][1] = s * (b * c - a * d);
-    R[0][2] = s * (b * d + a * c);
-    R[1][0] = s * (b * c + a * d);
-    R[1][1] = 1.0 - s * (b * b + d * d);
-    R[1][2] = s * (c * d - a * b);
-    R[2][0] = s * (b * d - a * c);
-    R[2][1] = s * (c * d + a * b);
-    R[2][2] = 1.0 - s * (b * b + c * c);
+    R[0][0] = __dadd_rn(1.0, -__dmul_rn(s, __dadd_rn(cc, dd)));
+    R[0][1] = __dmul_rn(s, __dadd_rn(bc, -ad));
+    R[0][2] = __dmul_rn(s, __dadd_rn(bd, ac));
+    R[1][0] = __dmul_rn(s, __dadd_rn(bc, ad));
+    R[1][1] = __dadd_rn(1.0, -__dmul_rn(s, __dadd_rn(bb, dd)));
+    R[1][2] = __dmul_rn(s, __dadd_rn(cd, -ab));
+    R[2][0] = __dmul_rn(s, __dadd_rn(bd, -ac));
+    R[2][1] = __dmul_rn(s, __dadd_rn(cd, ab));
+    R[2][2] = __dadd_rn(1.0, -__dmul_rn(s, __dadd_rn(bb, cc)));
     double sc[3], m[3];
     for (int k = 0; k < 3; ++k) {
         sc[k] = scale[3 * i + k];
@@ -278,16 +285,19 @@ __global__ __launch_bounds__(256) void k_records(const uint32_t *__restrict__ pe
     records[4 * j + 1] = r1;
     records[4 * j + 2] = r2;
     records[4 * j + 3] = r3;
-    // half extent along world axis k: sqrt(Q * sum_c (R_kc s_c)^2), padded
+    // half extent along world axis k: sqrt(Q * sum_c (R_kc s_c)^2), padded by
+    // 1e-5 relative and 1e-7 (1 + |m_k|) absolute, rounded outward
     for (int k = 0; k < 3; ++k) {
         double e2 = 0.0;
-        for (int cc = 0; cc < 3; ++cc) {
-            double v = R[k][cc] * sc[cc];
-            e2 += v * v;
+        for (int q = 0; q < 3; ++q) {
+            const double v = __dmul_rn(R[k][q], sc[q]);
+            e2 = __dadd_rn(e2, __dmul_rn(v, v));
         }
-        double e = sqrt(double(Q) * e2) * (1.0 + 1e-5) + 1e-7 * (1.0 + fabs(m[k]));
-        leaf_boxes[6 * j + k] = __double2float_rd(m[k] - e);
-        leaf_boxes[6 * j + 3 + k] = __double2float_ru(m[k] + e);
+        double e = __dsqrt_rn(__dmul_rn(double(Q), e2));
+        e = __dmul_rn(e, 1.0 + 1e-5);
+        e = __dadd_rn(e, __dmul_rn(1e-7, __dadd_rn(1.0, fabs(m[k]))));
+        leaf_boxes[6 * j + k] = __double2float_rd(__dadd_rn(m[k], -e));
+        leaf_boxes[6 * j + 3 + k] = __double2float_ru(__dadd_rn(m[k], e));
     }
     inv[i] = int32_t(j);
 }
@@ -474,6 +484,400 @@ __global__ __launch_bounds__(256) void k_tri_records(const uint32_t *__restrict_
     inv[i] = int32_t(j);
 }
 
+// -------------------------------------------------------------------- PLOC
+//
+// Locally-ordered agglomerative clustering (Meister and Bittner, 2018) over
+// the leaves in Morton order. Each iteration every cluster finds its nearest
+// neighbour within kPlocR positions (distance: half the surface area of the
+// union box); mutual nearest neighbours merge into a new internal node, which
+// takes the lower position, and the survivors are compacted in order. The
+// k-th merge of the build becomes node n - 2 - k, so the root is node 0 and
+// the top of the tree sits at the front of the node array.
+//
+// Large cluster counts run as grid-wide iterations (nearest neighbours +
+// merge codes + per-chunk counts, then prefix + scatter), each kernel reading
+// its cluster count from the control array so the launch sequence is fixed
+// (graph-capturable); the last few thousand clusters are finished by one
+// workgroup in LDS. Ties follow a symmetric total order on pairs (distance,
+// offset, parity of the lower end, lower end), so the best pair is always
+// mutual and every iteration merges; from iteration ploc_cap(n) clusters are
+// paired by position, which bounds the iteration count.
+
+struct PlocCtrl {
+    int32_t n, created, buf, pad;
+};
+
+__device__ inline float ploc_dist(float alx, float aly, float alz, float ahx, float ahy, float ahz, float blx,
+                                  float bly, float blz, float bhx, float bhy, float bhz)
+{
+    const float ex = __fsub_rn(fmaxf(ahx, bhx), fminf(alx, blx));
+    const float ey = __fsub_rn(fmaxf(ahy, bhy), fminf(aly, bly));
+    const float ez = __fsub_rn(fmaxf(ahz, bhz), fminf(alz, blz));
+    const float d = __fadd_rn(__fadd_rn(__fmul_rn(ex, ey), __fmul_rn(ey, ez)), __fmul_rn(ez, ex));
+    return d == d ? d : __builtin_huge_valf();
+}
+
+// Nearest neighbour of position i among [i - R, i + R] of n clusters; boxes
+// are read through `at(j)` (a 6-float box of position j). The pair order
+// (distance, offset, parity of the lower end, lower end) is one 64-bit key:
+// order-preserving distance bits, then offset, parity and side (for a given
+// offset the left candidate is the lower end).
+__device__ inline uint32_t ordered_bits(float d)
+{
+    const uint32_t u = __float_as_uint(d + 0.0f);  // -0 -> +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+template <typename BoxAt>
+__device__ inline int32_t ploc_nearest(int64_t i, int64_t n, BoxAt at)
+{
+    float a[6];
+    at(i, a);
+    int32_t best = -1;
+    uint64_t bk = ~0ull;
+#pragma unroll
+    for (int off = 1; off <= kPlocR; ++off) {
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+            const int64_t j = side ? i + off : i - off;
+            if (j < 0 || j >= n) continue;
+            float b[6];
+            at(j, b);
+            const float d = ploc_dist(a[0], a[1], a[2], a[3], a[4], a[5], b[0], b[1], b[2], b[3], b[4], b[5]);
+            const uint32_t par = uint32_t(side ? i : j) & 1u;
+            const uint64_t key = (uint64_t(ordered_bits(d)) << 32) | (uint32_t(off) << 2) | (par << 1) | uint32_t(side);
+            if (key < bk) {
+                bk = key;
+                best = int32_t(j);
+            }
+        }
+    }
+    return best;
+}
+
+// Exclusive scan of two counts over a workgroup of THREADS; ws holds 2 ints
+// per wave. Returns the workgroup totals. Ends with a barrier (ws reusable).
+template <int THREADS>
+__device__ inline void block_scan2(int a, int b, int &ea, int &eb, int &ta, int &tb, int *ws)
+{
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    int ia = a, ib = b;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int xa = __shfl_up(ia, d), xb = __shfl_up(ib, d);
+        if (lane >= d) {
+            ia += xa;
+            ib += xb;
+        }
+    }
+    if (lane == kWave - 1) {
+        ws[2 * wave] = ia;
+        ws[2 * wave + 1] = ib;
+    }
+    __syncthreads();
+    int pa = 0, pb = 0;
+    ta = 0;
+    tb = 0;
+#pragma unroll
+    for (int w = 0; w < THREADS / kWave; ++w) {
+        const int va = ws[2 * w], vb = ws[2 * w + 1];
+        if (w < wave) {
+            pa += va;
+            pb += vb;
+        }
+        ta += va;
+        tb += vb;
+    }
+    ea = pa + ia - a;
+    eb = pb + ib - b;
+    __syncthreads();
+}
+
+__device__ inline void write_node(float4 *__restrict__ nodes, int64_t id, const float *bl, const float *br, int32_t rl,
+                                  int32_t rr)
+{
+    float4 *nd = nodes + 4 * id;
+    nd[0] = make_float4(bl[0], bl[1], bl[2], bl[3]);
+    nd[1] = make_float4(bl[4], bl[5], br[0], br[1]);
+    nd[2] = make_float4(br[2], br[3], br[4], br[5]);
+    nd[3] = make_float4(__int_as_float(rl), __int_as_float(rr), 0.0f, 0.0f);
+}
+
+// Clusters of iteration 0: the leaves (buffer 0), and the control entry.
+__global__ __launch_bounds__(256) void k_ploc_init(const float *__restrict__ leaf_boxes, int64_t n,
+                                                   float *__restrict__ box, int32_t *__restrict__ ref,
+                                                   PlocCtrl *ctrl)
+{
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j == 0) ctrl[0] = PlocCtrl{int32_t(n), 0, 0, 0};
+    if (j >= n) return;
+    for (int k = 0; k < 6; ++k) box[k * n + j] = leaf_boxes[6 * j + k];
+    ref[j] = ~int32_t(j);
+}
+
+// Grid iteration, step 1: nearest neighbours of a chunk and of kPlocR
+// positions either side (from boxes staged in LDS with 2 kPlocR margin),
+// then the merge code of each position (-1 keep, -2 merged into a lower
+// position, m > i: merges with m into a new node) and the chunk's counts.
+__global__ __launch_bounds__(kPlocThreads) void k_ploc_nn(const float *__restrict__ box_all, const PlocCtrl *ctrl,
+                                                          int it, int64_t N, int32_t *__restrict__ pm,
+                                                          int32_t *__restrict__ blk)
+{
+    constexpr int W = kPlocChunk + 4 * kPlocR;
+    constexpr int M = kPlocChunk + 2 * kPlocR;
+    __shared__ float sb[6][W];
+    __shared__ int32_t snn[M];
+    __shared__ int ws[2 * kPlocThreads / kWave];
+    const PlocCtrl c = ctrl[it];
+    const int64_t n = c.n;
+    if (n <= kPlocLocal) return;
+    const int64_t base = int64_t(blockIdx.x) * kPlocChunk;
+    if (base >= n) return;
+    const float *box = box_all + size_t(c.buf) * 6 * N;
+    const int64_t w0 = base - 2 * kPlocR;
+    for (int t = threadIdx.x; t < W; t += kPlocThreads) {
+        const int64_t i = w0 + t;
+        const bool in = i >= 0 && i < n;
+        for (int k = 0; k < 6; ++k) sb[k][t] = in ? box[k * N + i] : 0.0f;
+    }
+    __syncthreads();
+    auto at = [&](int64_t j, float *b) {
+        const int64_t t = j - w0;
+        for (int k = 0; k < 6; ++k) b[k] = sb[k][t];
+    };
+    for (int t = threadIdx.x; t < M; t += kPlocThreads) {
+        const int64_t i = base - kPlocR + t;
+        snn[t] = (i >= 0 && i < n) ? ploc_nearest(i, n, at) : -1;
+    }
+    __syncthreads();
+    int keep = 0, make = 0;
+    for (int t = threadIdx.x; t < kPlocChunk; t += kPlocThreads) {
+        const int64_t i = base + t;
+        if (i >= n) break;
+        const int32_t m = snn[t + kPlocR];
+        int32_t code = -1;
+        if (m >= 0 && snn[m - (base - kPlocR)] == int32_t(i)) code = m > i ? m : -2;
+        pm[i] = code;
+        keep += code != -2;
+        make += code >= 0;
+    }
+    int ek, em, tk, tm;
+    block_scan2<kPlocThreads>(keep, make, ek, em, tk, tm, ws);
+    if (threadIdx.x == 0) {
+        blk[2 * blockIdx.x] = tk;
+        blk[2 * blockIdx.x + 1] = tm;
+    }
+}
+
+// Grid iteration, step 2: each chunk sums the counts of the chunks before it,
+// scans its own positions (four consecutive per thread), writes the survivors
+// to the other buffer and the new nodes; the last chunk writes the next
+// control entry.
+__global__ __launch_bounds__(kPlocThreads) void k_ploc_scatter(float *__restrict__ box_all, int32_t *__restrict__ ref_all,
+                                                               PlocCtrl *ctrl, int it, int64_t N,
+                                                               const int32_t *__restrict__ pm,
+                                                               const int32_t *__restrict__ blk,
+                                                               float4 *__restrict__ nodes)
+{
+    __shared__ int ws[2 * kPlocThreads / kWave];
+    const PlocCtrl c = ctrl[it];
+    const int64_t n = c.n;
+    if (n <= kPlocLocal) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) ctrl[it + 1] = c;
+        return;
+    }
+    const int64_t nb = (n + kPlocChunk - 1) / kPlocChunk;
+    const int64_t b = blockIdx.x;
+    if (b >= nb) return;
+    int kp = 0, mp = 0;
+    for (int64_t q = threadIdx.x; q < b; q += kPlocThreads) {
+        kp += blk[2 * q];
+        mp += blk[2 * q + 1];
+    }
+    int e0, e1;
+    block_scan2<kPlocThreads>(kp, mp, e0, e1, kp, mp, ws);
+    constexpr int E = kPlocChunk / kPlocThreads;
+    const int64_t i0 = b * kPlocChunk + int64_t(threadIdx.x) * E;
+    int32_t code[E];
+    int lk = 0, lm = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        code[e] = i0 + e < n ? pm[i0 + e] : -2;
+        lk += code[e] != -2;
+        lm += code[e] >= 0;
+    }
+    int ok, om, tk, tm;
+    block_scan2<kPlocThreads>(lk, lm, ok, om, tk, tm, ws);
+    const float *sbx = box_all + size_t(c.buf) * 6 * N;
+    float *dbx = box_all + size_t(1 - c.buf) * 6 * N;
+    const int32_t *sref = ref_all + size_t(c.buf) * N;
+    int32_t *dref = ref_all + size_t(1 - c.buf) * N;
+    int64_t pos = int64_t(kp) + ok;
+    int64_t made = int64_t(c.created) + mp + om;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        const int64_t i = i0 + e;
+        if (code[e] == -2) continue;
+        float bi[6];
+        for (int k = 0; k < 6; ++k) bi[k] = sbx[k * N + i];
+        int32_t ri = sref[i];
+        if (code[e] >= 0) {
+            const int64_t m = code[e];
+            float bm[6];
+            for (int k = 0; k < 6; ++k) bm[k] = sbx[k * N + m];
+            const int64_t id = N - 2 - made;
+            ++made;
+            if (id >= 0) write_node(nodes, id, bi, bm, ri, sref[m]);
+            for (int k = 0; k < 3; ++k) {
+                bi[k] = fminf(bi[k], bm[k]);
+                bi[3 + k] = fmaxf(bi[3 + k], bm[3 + k]);
+            }
+            ri = int32_t(id);
+        }
+        for (int k = 0; k < 6; ++k) dbx[k * N + pos] = bi[k];
+        dref[pos] = ri;
+        ++pos;
+    }
+    if (b == nb - 1 && threadIdx.x == 0)
+        ctrl[it + 1] = PlocCtrl{kp + tk, int32_t(c.created + mp + tm), 1 - c.buf, 0};
+}
+
+// The remaining iterations in one workgroup. Positions are compacted in
+// place, a chunk of kPlocFinishThreads * 2 at a time: every position of a
+// chunk (and its merge partner, which lies above it) is read before any is
+// written, and a survivor's new position never exceeds its old one, so no
+// unread position is overwritten.
+template <typename Arr>
+__device__ inline void ploc_finish_loop(Arr A, int64_t n, int64_t made, int t, int cap, int64_t N,
+                                        float4 *__restrict__ nodes, int *ws)
+{
+    constexpr int E = 2;
+    constexpr int CH = kPlocFinishThreads * E;
+    auto at = [&](int64_t j, float *b) {
+        for (int k = 0; k < 6; ++k) b[k] = A.box(k, j);
+    };
+    while (n > 1) {
+        const bool forced = t >= cap;
+        for (int64_t i = threadIdx.x; i < n; i += kPlocFinishThreads)
+            A.nn(i) = forced ? ((i ^ 1) < n ? int32_t(i ^ 1) : -1) : ploc_nearest(i, n, at);
+        __syncthreads();
+        int64_t kc = 0, mc = 0;
+        for (int64_t base = 0; base < n; base += CH) {
+            const int64_t i0 = base + int64_t(threadIdx.x) * E;
+            int32_t code[E], ri[E], rm[E];
+            float bi[E][6], bm[E][6];
+            int lk = 0, lm = 0;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const int64_t i = i0 + e;
+                code[e] = -2;
+                if (i < n) {
+                    const int32_t m = A.nn(i);
+                    code[e] = (m >= 0 && A.nn(m) == int32_t(i)) ? (m > i ? m : -2) : -1;
+                }
+                if (code[e] != -2) {
+                    for (int k = 0; k < 6; ++k) bi[e][k] = A.box(k, i);
+                    ri[e] = A.ref(i);
+                }
+                if (code[e] >= 0) {
+                    for (int k = 0; k < 6; ++k) bm[e][k] = A.box(k, code[e]);
+                    rm[e] = A.ref(code[e]);
+                }
+                lk += code[e] != -2;
+                lm += code[e] >= 0;
+            }
+            int ok, om, tk, tm;
+            block_scan2<kPlocFinishThreads>(lk, lm, ok, om, tk, tm, ws);
+            int64_t pos = kc + ok, id_n = made + mc + om;
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                if (code[e] == -2) continue;
+                int32_t r = ri[e];
+                if (code[e] >= 0) {
+                    const int64_t id = N - 2 - id_n;
+                    ++id_n;
+                    if (id >= 0) write_node(nodes, id, bi[e], bm[e], ri[e], rm[e]);
+                    for (int k = 0; k < 3; ++k) {
+                        bi[e][k] = fminf(bi[e][k], bm[e][k]);
+                        bi[e][3 + k] = fmaxf(bi[e][3 + k], bm[e][3 + k]);
+                    }
+                    r = int32_t(id);
+                }
+                for (int k = 0; k < 6; ++k) A.box(k, pos) = bi[e][k];
+                A.ref(pos) = r;
+                ++pos;
+            }
+            kc += tk;
+            mc += tm;
+            __syncthreads();
+        }
+        n = kc;
+        made += mc;
+        ++t;
+    }
+}
+
+struct PlocLds {
+    float (*b)[kPlocLocal];
+    int32_t *r, *q;
+    __device__ float &box(int k, int64_t j) const { return b[k][j]; }
+    __device__ int32_t &ref(int64_t j) const { return r[j]; }
+    __device__ int32_t &nn(int64_t j) const { return q[j]; }
+};
+
+struct PlocGlobal {
+    float *b;
+    int32_t *r, *q;
+    int64_t N;
+    __device__ float &box(int k, int64_t j) const { return b[k * N + j]; }
+    __device__ int32_t &ref(int64_t j) const { return r[j]; }
+    __device__ int32_t &nn(int64_t j) const { return q[j]; }
+};
+
+// Finish of the clustering when at most kPlocLocal clusters remain (the usual
+// case): clusters staged in LDS. Writes the root box.
+__global__ __launch_bounds__(kPlocFinishThreads) void k_ploc_finish_lds(const float *__restrict__ box_all,
+                                                                        const int32_t *__restrict__ ref_all,
+                                                                        const PlocCtrl *ctrl, int G, int cap, int64_t N,
+                                                                        float4 *__restrict__ nodes, WsHeader *h)
+{
+    __shared__ float sb[6][kPlocLocal];
+    __shared__ int32_t sref[kPlocLocal], snn[kPlocLocal];
+    __shared__ int ws[2 * kPlocFinishThreads / kWave];
+    const PlocCtrl c = ctrl[G];
+    const int64_t n = c.n;
+    if (n > kPlocLocal) return;
+    const float *gbox = box_all + size_t(c.buf) * 6 * N;
+    const int32_t *gref = ref_all + size_t(c.buf) * N;
+    for (int64_t i = threadIdx.x; i < n; i += kPlocFinishThreads) {
+        for (int k = 0; k < 6; ++k) sb[k][i] = gbox[k * N + i];
+        sref[i] = gref[i];
+    }
+    __syncthreads();
+    ploc_finish_loop(PlocLds{sb, sref, snn}, n, c.created, G, cap, N, nodes, ws);
+    if (threadIdx.x < 6) h->root_box[threadIdx.x] = sb[threadIdx.x][0];
+}
+
+// The same from global memory, in place, for more than kPlocLocal clusters
+// (only when the grid iterations left that many: slow, but bounded by the
+// pairing cap).
+__global__ __launch_bounds__(kPlocFinishThreads) void k_ploc_finish_global(float *__restrict__ box_all,
+                                                                           int32_t *__restrict__ ref_all,
+                                                                           int32_t *__restrict__ pm,
+                                                                           const PlocCtrl *ctrl, int G, int cap,
+                                                                           int64_t N, float4 *__restrict__ nodes,
+                                                                           WsHeader *h)
+{
+    __shared__ int ws[2 * kPlocFinishThreads / kWave];
+    const PlocCtrl c = ctrl[G];
+    const int64_t n = c.n;
+    if (n <= kPlocLocal) return;
+    float *gbox = box_all + size_t(c.buf) * 6 * N;
+    int32_t *gref = ref_all + size_t(c.buf) * N;
+    ploc_finish_loop(PlocGlobal{gbox, gref, pm, N}, n, c.created, G, cap, N, nodes, ws);
+    if (threadIdx.x < 6) h->root_box[threadIdx.x] = gbox[threadIdx.x * N];
+}
+
 // ------------------------------------------------------------------- host
 
 static inline int blocks_for(int64_t n, int threads) { return int((n + threads - 1) / threads); }
@@ -483,7 +887,7 @@ static inline int blocks_for(int64_t n, int threads) { return int((n + threads -
 // order once the permutation is known.
 template <typename RecordsFn>
 static int build_core(int64_t n, const float *points, const float *scale, const float *quat, const float *opacity,
-                      const float *rgb, char *ws, hipStream_t st, RecordsFn records_fn, bool init_header)
+                      const float *rgb, char *ws, hipStream_t st, RecordsFn records_fn, bool init_header, bool lbvh)
 {
     Layout L = make_layout(n);
     WsHeader *h = reinterpret_cast<WsHeader *>(ws + L.header);
@@ -519,7 +923,23 @@ static int build_core(int64_t n, const float *points, const float *scale, const 
         t = va; va = vb; vb = t;
     }
     records_fn(vals, records, leaf_boxes, inv, h);
-    if (n >= 2) {
+    if (n >= 2 && !lbvh) {
+        float *pbox = reinterpret_cast<float *>(ws + L.ploc_box);
+        int32_t *pref = reinterpret_cast<int32_t *>(ws + L.ploc_ref);
+        int32_t *pm = reinterpret_cast<int32_t *>(ws + L.ploc_pm);
+        int32_t *blk = reinterpret_cast<int32_t *>(ws + L.ploc_blk);
+        PlocCtrl *ctrl = reinterpret_cast<PlocCtrl *>(ws + L.ploc_ctrl);
+        k_ploc_init<<<bgrid, 256, 0, st>>>(leaf_boxes, n, pbox, pref, ctrl);
+        const int G = ploc_global_iters(n);
+        const int nchunks = int(L.ploc_chunks);
+        for (int it = 0; it < G; ++it) {
+            k_ploc_nn<<<nchunks, kPlocThreads, 0, st>>>(pbox, ctrl, it, n, pm, blk);
+            k_ploc_scatter<<<nchunks, kPlocThreads, 0, st>>>(pbox, pref, ctrl, it, n, pm, blk, nodes);
+        }
+        k_ploc_finish_lds<<<1, kPlocFinishThreads, 0, st>>>(pbox, pref, ctrl, G, ploc_cap(n), n, nodes, h);
+        if (G > 0)
+            k_ploc_finish_global<<<1, kPlocFinishThreads, 0, st>>>(pbox, pref, pm, ctrl, G, ploc_cap(n), n, nodes, h);
+    } else if (n >= 2) {
         k_fill_u32<<<blocks_for(L.n_int, 256) < 2048 ? blocks_for(L.n_int, 256) : 2048, 256, 0, st>>>(visit, L.n_int,
                                                                                                        0u);
         k_karras<<<blocks_for(n - 1, 256), 256, 0, st>>>(codes, n, nodes, parent);
@@ -533,14 +953,14 @@ static int build_core(int64_t n, const float *points, const float *scale, const 
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 
-int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st)
+int launch_build(const rs_gaussians *g, float Q, bool lbvh, char *ws, hipStream_t st)
 {
     const int64_t n = g->n;
     const int bgrid = blocks_for(n, 256);
     auto rec = [&](const uint32_t *perm, float4 *records, float *leaf_boxes, int32_t *inv, WsHeader *) {
         k_records<<<bgrid, 256, 0, st>>>(perm, g->mean, g->scale, g->quat, g->opacity, n, Q, records, leaf_boxes, inv);
     };
-    return build_core(n, g->mean, g->scale, g->quat, g->opacity, g->rgb, ws, st, rec, true);
+    return build_core(n, g->mean, g->scale, g->quat, g->opacity, g->rgb, ws, st, rec, true, lbvh);
 }
 
 int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st)
@@ -557,7 +977,7 @@ int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st)
         k_tri_records<<<bgrid, 256, 0, st>>>(perm, m->verts, m->tris, m->material, n, m->n_verts, records, leaf_boxes,
                                              inv, hh);
     };
-    return build_core(n, cent, nullptr, nullptr, nullptr, nullptr, ws, st, rec, false);
+    return build_core(n, cent, nullptr, nullptr, nullptr, nullptr, ws, st, rec, false, false);
 }
 
 }  // namespace rs

@@ -29,6 +29,30 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 8;  // keys per thread per sort tile
 constexpr int kSortTile = kSortBlock * kSortItems;
 
+// PLOC build: neighbourhood radius, clusters per workgroup of the global
+// iterations, the finish kernel's LDS capacity, workgroup sizes.
+constexpr int kPlocR = 8;
+constexpr int kPlocChunk = 2048;
+constexpr int kPlocThreads = 512;
+constexpr int kPlocLocal = 4096;
+constexpr int kPlocFinishThreads = 1024;
+constexpr int kPlocMaxIters = 512;  // size of the per-iteration control array
+
+// Global (grid-wide) PLOC iterations launched for n clusters: 0 when the
+// finish kernel can take them all, else 10 per halving down to kPlocLocal
+// (the clustering removes about a tenth of the clusters per iteration).
+inline int ploc_global_iters(int64_t n)
+{
+    if (n <= kPlocLocal) return 0;
+    const int64_t c = (n + kPlocLocal - 1) / kPlocLocal;
+    int l = 0;
+    while ((int64_t(1) << l) < c) ++l;
+    return 10 * l;
+}
+// Iteration from which clusters are paired by position instead of by
+// distance, so every build ends after a bounded number of iterations.
+inline int ploc_cap(int64_t n) { return 256 + ploc_global_iters(n); }
+
 // Device status bits (sticky, OR-ed by kernels).
 constexpr int kStatusStack = 1;
 constexpr int kStatusNonfinite = 2;
@@ -55,8 +79,9 @@ struct WsHeader {
 static_assert(sizeof(WsHeader) == 256, "header size");
 
 struct Layout {
-    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, ibox, keys_alt, vals_alt, hist, totals, gacc, total;
-    int64_t n, n_int, sort_blocks;
+    size_t header, records, nodes, gidx, inv, codes, leaf_boxes, parent, visit, ibox, keys_alt, vals_alt, hist, totals, gacc;
+    size_t ploc_box, ploc_ref, ploc_pm, ploc_blk, ploc_ctrl, total;
+    int64_t n, n_int, sort_blocks, ploc_chunks;
 };
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -90,6 +115,14 @@ inline Layout make_layout(int64_t n)
     L.hist = take(size_t(256) * L.sort_blocks * 4);
     L.totals = take(size_t(512) * 4);
     L.gacc = take(size_t(nn) * 64);
+    // PLOC clusters: two buffers of boxes (6 float arrays of n each) and refs,
+    // the merge code per position, per-chunk counts, per-iteration control
+    L.ploc_chunks = (nn + kPlocChunk - 1) / kPlocChunk;
+    L.ploc_box = take(size_t(nn) * 48);
+    L.ploc_ref = take(size_t(nn) * 8);
+    L.ploc_pm = take(size_t(nn) * 4);
+    L.ploc_blk = take(size_t(L.ploc_chunks) * 8);
+    L.ploc_ctrl = take(size_t(kPlocMaxIters) * 16);
     L.total = off;
     return L;
 }
@@ -158,7 +191,7 @@ inline StateLayout state_layout(int64_t n, int32_t cap)
     return L;
 }
 
-int launch_build(const rs_gaussians *g, float Q, char *ws, hipStream_t st);
+int launch_build(const rs_gaussians *g, float Q, bool lbvh, char *ws, hipStream_t st);
 int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets, bool bwd,
                 hipStream_t st, bool list_adjoint = false);
 int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,

@@ -1,5 +1,6 @@
 """BVH build on the GPU against the CPU reference: Morton codes, sorted
-permutation and radix-tree topology bit-exact; boxes conservative."""
+permutation, leaf boxes, the PLOC tree (topology and child boxes) and the
+radix-tree topology bit-exact; boxes conservative."""
 
 import numpy as np
 import pytest
@@ -11,28 +12,77 @@ from oracle import oracle as O
 pytestmark = pytest.mark.gpu
 
 
-def _build(scene, Q=11.3449):
+def _build(scene, Q=11.3449, lbvh=False):
     from tests._gpu import gaussians
-    from paper_2501_19196_amd import renderer as R
+    from paper_2501_19196_amd import renderer as R, _lib as L
     g = gaussians(scene)
-    bvh = R.build_bvh(g, R.Params(Q=Q))
+    bvh = R.build_bvh(g, R.Params(Q=Q, flags=L.RS_BUILD_LBVH if lbvh else 0))
     torch.cuda.synchronize()
     return R.download(bvh), R.read_status(bvh)
 
 
-@pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups"])
-def test_morton_sort_topology_bit_exact(which):
-    print("case", which, flush=True)
+def _chain(n):
+    """Gaussians along x with slowly growing isotropic scale: each leaf's
+    nearest cluster is its left neighbour, so clustering merges about one pair
+    per iteration and reaches the pairing cap."""
+    from synthetic.scenes import Scene
+    rng = np.random.default_rng(n)
+    mean = np.zeros((n, 3), np.float32)
+    mean[:, 0] = np.arange(n)
+    scale = np.repeat((0.3 + 0.001 * np.arange(n))[:, None], 3, 1).astype(np.float32)
+    quat = np.tile(np.array([[1, 0, 0, 0]], np.float32), (n, 1))
+    return Scene(mean, scale, quat, np.full(n, 0.5, np.float32), rng.uniform(size=(n, 3)).astype(np.float32))
+
+
+def _scene(which):
     if which == "config1":
-        sc = scenes.scene_config1()
-    elif which == "clusters100k":
-        sc = scenes.scene_config2(n=100_000)
-    elif which == "ragged":
-        sc = scenes.random_scene(7, 2048 * 3 + 17)  # several sort tiles plus a ragged tail
-    else:
+        return scenes.scene_config1()
+    if which == "clusters100k":
+        return scenes.scene_config2(n=100_000)
+    if which == "ragged":
+        return scenes.random_scene(7, 2048 * 3 + 17)  # several sort tiles plus a ragged tail
+    if which == "dups":
         sc = scenes.random_scene(8, 5000)
         sc.mean[::3] = sc.mean[0]  # many identical codes
+        return sc
+    if which == "equal_boxes":
+        sc = scenes.random_scene(12, 4500)
+        sc.mean[:] = sc.mean[0]
+        sc.scale[:] = sc.scale[0]
+        sc.quat[:] = sc.quat[0]
+        return sc
+    if which == "local_edge":
+        return scenes.random_scene(13, 4097)  # one cluster more than the single-workgroup finish holds
+    if which == "chain600":
+        return _chain(600)
+    if which == "chain20k":
+        return _chain(20_000)  # leaves the finish kernel more clusters than fit in LDS
+    raise ValueError(which)
+
+
+@pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups", "equal_boxes", "local_edge",
+                                   "chain600", "chain20k"])
+def test_leaf_boxes_and_ploc_tree_bit_exact(which):
+    print("case ploc", which, flush=True)
+    sc = _scene(which)
     got, status = _build(sc)
+    assert status == 0
+    codes, _, _ = O.morton_codes(sc.mean)
+    _, perm = O.sort_codes(codes)
+    np.testing.assert_array_equal(got["perm"], perm)
+    lb = O.leaf_boxes(sc.mean, sc.scale, sc.quat, perm)
+    np.testing.assert_array_equal(got["leaf_boxes"], lb)
+    child, boxes, _ = O.ploc(lb)
+    np.testing.assert_array_equal(got["child"], child)
+    np.testing.assert_array_equal(got["boxes"], boxes)
+
+
+@pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups"])
+def test_morton_sort_topology_bit_exact(which):
+    """The radix-tree builder (RS_BUILD_LBVH)."""
+    print("case lbvh", which, flush=True)
+    sc = _scene(which)
+    got, status = _build(sc, lbvh=True)
     assert status == 0
     codes, lo, hi = O.morton_codes(sc.mean)
     np.testing.assert_array_equal(got["bounds"][:3], lo)
@@ -46,9 +96,10 @@ def test_morton_sort_topology_bit_exact(which):
     np.testing.assert_array_equal(gc, want)
 
 
-def test_boxes_are_conservative():
+@pytest.mark.parametrize("lbvh", [False, True])
+def test_boxes_are_conservative(lbvh):
     sc = scenes.random_scene(9, 3000)
-    got, _ = _build(sc)
+    got, _ = _build(sc, lbvh=lbvh)
     perm = got["perm"]
     lb = got["leaf_boxes"]
     Q = 11.3449
@@ -78,16 +129,20 @@ def test_boxes_are_conservative():
 
 
 @pytest.mark.parametrize("n", [1, 2, 3])
-def test_tiny_scenes(n):
+@pytest.mark.parametrize("lbvh", [False, True])
+def test_tiny_scenes(n, lbvh):
     sc = scenes.random_scene(10, n)
-    got, status = _build(sc)
+    got, status = _build(sc, lbvh=lbvh)
     assert status == 0
     codes, _, _ = O.morton_codes(sc.mean)
     s, perm = O.sort_codes(codes)
     np.testing.assert_array_equal(got["perm"], perm)
-    if n >= 2:
+    if n >= 2 and lbvh:
         child, leaf = O.radix_tree(s)
         np.testing.assert_array_equal(got["child"], np.where(leaf, ~child, child))
+    elif n >= 2:
+        child, _, _ = O.ploc(O.leaf_boxes(sc.mean, sc.scale, sc.quat, perm))
+        np.testing.assert_array_equal(got["child"], child)
 
 
 def test_nonfinite_input_sets_status():

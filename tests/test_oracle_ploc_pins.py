@@ -52,7 +52,7 @@ def test_leaf_boxes_match_the_support_function():
     1e-7 (1 + |m|) absolute padding and rounds outward."""
     sc = scenes.random_scene(21, 500)
     lb, perm = _sorted_boxes(sc)
-    Q = O.Q_DEFAULT
+    Q = float(np.float32(O.Q_DEFAULT))  # the float32 knob
     for j in range(sc.n):
         i = perm[j]
         R = O.rotation(sc.quat[i].astype(np.float64))
