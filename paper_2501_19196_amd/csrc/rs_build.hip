@@ -555,6 +555,22 @@ __device__ inline int32_t ploc_nearest(int64_t i, int64_t n, BoxAt at)
     return best;
 }
 
+// The same order from the pair side: the distance of pair (p, p + off) is
+// computed once and offered to both ends as a 64-bit key (side bit 1: the
+// candidate lies to the right); the smallest key a position receives names
+// its nearest neighbour.
+__device__ inline uint64_t pair_key(float d, int off, int64_t lower, uint32_t right)
+{
+    return (uint64_t(ordered_bits(d)) << 32) | (uint32_t(off) << 2) | ((uint32_t(lower) & 1u) << 1) | right;
+}
+
+__device__ inline int32_t key_neighbour(uint64_t key, int64_t i)
+{
+    if (key == ~0ull) return -1;
+    const int off = int(key >> 2) & 15;
+    return int32_t((key & 1ull) ? i + off : i - off);
+}
+
 // Exclusive scan of two counts over a workgroup of THREADS; ws holds 2 ints
 // per wave. Returns the workgroup totals. Ends with a barrier (ws reusable).
 template <int THREADS>
@@ -624,9 +640,8 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc_nn(const float *__restric
                                                           int32_t *__restrict__ blk)
 {
     constexpr int W = kPlocChunk + 4 * kPlocR;
-    constexpr int M = kPlocChunk + 2 * kPlocR;
     __shared__ float sb[6][W];
-    __shared__ int32_t snn[M];
+    __shared__ unsigned long long skey[W];
     __shared__ int ws[2 * kPlocThreads / kWave];
     const PlocCtrl c = ctrl[it];
     const int64_t n = c.n;
@@ -639,24 +654,35 @@ __global__ __launch_bounds__(kPlocThreads) void k_ploc_nn(const float *__restric
         const int64_t i = w0 + t;
         const bool in = i >= 0 && i < n;
         for (int k = 0; k < 6; ++k) sb[k][t] = in ? box[k * N + i] : 0.0f;
+        skey[t] = ~0ull;
     }
     __syncthreads();
-    auto at = [&](int64_t j, float *b) {
-        const int64_t t = j - w0;
-        for (int k = 0; k < 6; ++k) b[k] = sb[k][t];
-    };
-    for (int t = threadIdx.x; t < M; t += kPlocThreads) {
-        const int64_t i = base - kPlocR + t;
-        snn[t] = (i >= 0 && i < n) ? ploc_nearest(i, n, at) : -1;
+    // every pair inside the window: positions [base - R, base + chunk + R) see all their candidates
+    for (int t = threadIdx.x; t < W; t += kPlocThreads) {
+        const int64_t p = w0 + t;
+        if (p < 0 || p >= n) continue;
+        const float a0 = sb[0][t], a1 = sb[1][t], a2 = sb[2][t], a3 = sb[3][t], a4 = sb[4][t], a5 = sb[5][t];
+        uint64_t kp = ~0ull;
+#pragma unroll
+        for (int off = 1; off <= kPlocR; ++off) {
+            const int tq = t + off;
+            if (tq >= W || p + off >= n) break;
+            const float d = ploc_dist(a0, a1, a2, a3, a4, a5, sb[0][tq], sb[1][tq], sb[2][tq], sb[3][tq], sb[4][tq],
+                                      sb[5][tq]);
+            const uint64_t kr = pair_key(d, off, p, 1u);
+            kp = kr < kp ? kr : kp;
+            atomicMin(&skey[tq], (unsigned long long)(kr ^ 1ull));
+        }
+        atomicMin(&skey[t], (unsigned long long)kp);
     }
     __syncthreads();
     int keep = 0, make = 0;
     for (int t = threadIdx.x; t < kPlocChunk; t += kPlocThreads) {
         const int64_t i = base + t;
         if (i >= n) break;
-        const int32_t m = snn[t + kPlocR];
+        const int32_t m = key_neighbour(skey[t + 2 * kPlocR], i);
         int32_t code = -1;
-        if (m >= 0 && snn[m - (base - kPlocR)] == int32_t(i)) code = m > i ? m : -2;
+        if (m >= 0 && key_neighbour(skey[m - w0], m) == int32_t(i)) code = m > i ? m : -2;
         pm[i] = code;
         keep += code != -2;
         make += code >= 0;
@@ -753,13 +779,8 @@ __device__ inline void ploc_finish_loop(Arr A, int64_t n, int64_t made, int t, i
 {
     constexpr int E = 2;
     constexpr int CH = kPlocFinishThreads * E;
-    auto at = [&](int64_t j, float *b) {
-        for (int k = 0; k < 6; ++k) b[k] = A.box(k, j);
-    };
     while (n > 1) {
-        const bool forced = t >= cap;
-        for (int64_t i = threadIdx.x; i < n; i += kPlocFinishThreads)
-            A.nn(i) = forced ? ((i ^ 1) < n ? int32_t(i ^ 1) : -1) : ploc_nearest(i, n, at);
+        A.nearest_all(n, t >= cap);
         __syncthreads();
         int64_t kc = 0, mc = 0;
         for (int64_t base = 0; base < n; base += CH) {
@@ -817,12 +838,37 @@ __device__ inline void ploc_finish_loop(Arr A, int64_t n, int64_t made, int t, i
     }
 }
 
+// Cluster storage of the finish loop. nearest_all(n, forced) fills the
+// nearest neighbours of positions [0, n) (ends without a barrier), nn(i)
+// reads one back (-1: none). Forced: i pairs with i xor 1.
 struct PlocLds {
     float (*b)[kPlocLocal];
-    int32_t *r, *q;
+    int32_t *r;
+    unsigned long long *key;
     __device__ float &box(int k, int64_t j) const { return b[k][j]; }
     __device__ int32_t &ref(int64_t j) const { return r[j]; }
-    __device__ int32_t &nn(int64_t j) const { return q[j]; }
+    __device__ int32_t nn(int64_t i) const { return key_neighbour(key[i], i); }
+    __device__ void nearest_all(int64_t n, bool forced) const
+    {
+        for (int64_t i = threadIdx.x; i < n; i += kPlocFinishThreads)
+            key[i] = forced ? ((i ^ 1) < n ? ((1ull << 2) | ((i & 1) ? 0ull : 1ull)) : ~0ull) : ~0ull;
+        if (forced) return;
+        __syncthreads();
+        for (int64_t p = threadIdx.x; p < n; p += kPlocFinishThreads) {
+            const float a0 = b[0][p], a1 = b[1][p], a2 = b[2][p], a3 = b[3][p], a4 = b[4][p], a5 = b[5][p];
+            uint64_t kp = ~0ull;
+#pragma unroll
+            for (int off = 1; off <= kPlocR; ++off) {
+                const int64_t q = p + off;
+                if (q >= n) break;
+                const float d = ploc_dist(a0, a1, a2, a3, a4, a5, b[0][q], b[1][q], b[2][q], b[3][q], b[4][q], b[5][q]);
+                const uint64_t kr = pair_key(d, off, p, 1u);
+                kp = kr < kp ? kr : kp;
+                atomicMin(&key[q], (unsigned long long)(kr ^ 1ull));
+            }
+            atomicMin(&key[p], (unsigned long long)kp);
+        }
+    }
 };
 
 struct PlocGlobal {
@@ -831,7 +877,15 @@ struct PlocGlobal {
     int64_t N;
     __device__ float &box(int k, int64_t j) const { return b[k * N + j]; }
     __device__ int32_t &ref(int64_t j) const { return r[j]; }
-    __device__ int32_t &nn(int64_t j) const { return q[j]; }
+    __device__ int32_t nn(int64_t i) const { return q[i]; }
+    __device__ void nearest_all(int64_t n, bool forced) const
+    {
+        auto at = [&](int64_t j, float *bx) {
+            for (int k = 0; k < 6; ++k) bx[k] = b[k * N + j];
+        };
+        for (int64_t i = threadIdx.x; i < n; i += kPlocFinishThreads)
+            q[i] = forced ? ((i ^ 1) < n ? int32_t(i ^ 1) : -1) : ploc_nearest(i, n, at);
+    }
 };
 
 // Finish of the clustering when at most kPlocLocal clusters remain (the usual
@@ -842,7 +896,8 @@ __global__ __launch_bounds__(kPlocFinishThreads) void k_ploc_finish_lds(const fl
                                                                         float4 *__restrict__ nodes, WsHeader *h)
 {
     __shared__ float sb[6][kPlocLocal];
-    __shared__ int32_t sref[kPlocLocal], snn[kPlocLocal];
+    __shared__ int32_t sref[kPlocLocal];
+    __shared__ unsigned long long skey[kPlocLocal];
     __shared__ int ws[2 * kPlocFinishThreads / kWave];
     const PlocCtrl c = ctrl[G];
     const int64_t n = c.n;
@@ -854,7 +909,7 @@ __global__ __launch_bounds__(kPlocFinishThreads) void k_ploc_finish_lds(const fl
         sref[i] = gref[i];
     }
     __syncthreads();
-    ploc_finish_loop(PlocLds{sb, sref, snn}, n, c.created, G, cap, N, nodes, ws);
+    ploc_finish_loop(PlocLds{sb, sref, skey}, n, c.created, G, cap, N, nodes, ws);
     if (threadIdx.x < 6) h->root_box[threadIdx.x] = sb[threadIdx.x][0];
 }
 

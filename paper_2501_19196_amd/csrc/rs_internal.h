@@ -29,29 +29,32 @@ constexpr int kSortBlock = 256;
 constexpr int kSortItems = 8;  // keys per thread per sort tile
 constexpr int kSortTile = kSortBlock * kSortItems;
 
-// PLOC build: neighbourhood radius, clusters per workgroup of the global
-// iterations, the finish kernel's LDS capacity, workgroup sizes.
+// PLOC build: neighbourhood radius, clusters per workgroup of the grid-wide
+// iterations (small chunks keep every workgroup short once few clusters are
+// left), the finish kernel's LDS capacity, workgroup sizes.
 constexpr int kPlocR = 8;
-constexpr int kPlocChunk = 2048;
-constexpr int kPlocThreads = 512;
+constexpr int kPlocChunk = 512;
+constexpr int kPlocThreads = 256;
 constexpr int kPlocLocal = 4096;
 constexpr int kPlocFinishThreads = 1024;
 constexpr int kPlocMaxIters = 512;  // size of the per-iteration control array
 
-// Global (grid-wide) PLOC iterations launched for n clusters: 0 when the
-// finish kernel can take them all, else 10 per halving down to kPlocLocal
-// (the clustering removes about a tenth of the clusters per iteration).
-inline int ploc_global_iters(int64_t n)
+// ceil(log2(ceil(n / kPlocLocal))) for n > kPlocLocal, else 0
+inline int ploc_halvings(int64_t n)
 {
     if (n <= kPlocLocal) return 0;
     const int64_t c = (n + kPlocLocal - 1) / kPlocLocal;
     int l = 0;
     while ((int64_t(1) << l) < c) ++l;
-    return 10 * l;
+    return l;
 }
+// Grid-wide iterations launched for n clusters (the clustering removes about
+// a tenth of the clusters per iteration; whatever is left above kPlocLocal
+// afterwards is finished from global memory).
+inline int ploc_global_iters(int64_t n) { return 7 * ploc_halvings(n); }
 // Iteration from which clusters are paired by position instead of by
 // distance, so every build ends after a bounded number of iterations.
-inline int ploc_cap(int64_t n) { return 256 + ploc_global_iters(n); }
+inline int ploc_cap(int64_t n) { return 256 + 10 * ploc_halvings(n); }
 
 // Device status bits (sticky, OR-ed by kernels).
 constexpr int kStatusStack = 1;
