@@ -302,13 +302,17 @@ def main():
     achieved = dom_flops / (med[dom] * 1e-3) / 1e12
 
     # HBM traffic per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used
-    # only when they were taken on the current kernel source and this workload
+    # only when they were taken on the current render and BVH sources, this workload and,
+    # for the forward, this launch shape
     traffic = None
     try:
         import hashlib
         rec = json.load(open(os.path.join(ROOT, "profiles", "render_traffic.json")))
-        src = open(os.path.join(ROOT, "paper_2501_19196_amd", "csrc", "rs_render.hip"), "rb").read()
-        if rec.get("rs_render_sha256") == hashlib.sha256(src).hexdigest() and rec.get("workload") == w["name"]:
+        src = b"".join(open(os.path.join(ROOT, "paper_2501_19196_amd", "csrc", f), "rb").read()
+                       for f in rec["sources"])
+        lf = dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2), tile_width=pf.tile_width or 8)
+        if rec.get("kernel_sources_sha256") == hashlib.sha256(src).hexdigest() and rec.get("workload") == w["name"] \
+                and (dom == "bwd" or rec.get("launch_fwd") == lf):
             traffic = rec[f"render_{dom}_bytes"]
     except (OSError, KeyError, ValueError):
         traffic = None
