@@ -493,18 +493,17 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
         const int2 lr = *reinterpret_cast<const int2 *>(nd + 3);
         float ln, lf, rn, rf;
         child_slabs<OCT>(n0, n1, n2, sl, ln, lf, rn, rf);
-        // [max(near, t_lo), min(widened exit, t_hi)] non-empty
-        const bool hl = fmaxf(ln, t_lo) <= fminf(widen_exit(lf, sl.pad), t_hi_w);
-        const bool hr = fmaxf(rn, t_lo) <= fminf(widen_exit(rf, sl.pad), t_hi_w);
-        const uint64_t bl = live_mask & wave_ballot(hl);
-        const uint64_t br = live_mask & wave_ballot(hr);
+        // [max(near, t_lo), min(widened exit, t_hi)] non-empty, as three compares (t_lo <= t_hi
+        // holds for every live lane): no min/max of the loop-invariant bounds
+        const float lx = widen_exit(lf, sl.pad), rx = widen_exit(rf, sl.pad);
+        const uint64_t bl = live_mask & wave_ballot(ln <= lx) & wave_ballot(ln <= t_hi_w) & wave_ballot(t_lo <= lx);
+        const uint64_t br = live_mask & wave_ballot(rn <= rx) & wave_ballot(rn <= t_hi_w) & wave_ballot(t_lo <= rx);
         const int32_t left = lr.x, right = lr.y;
-        const uint32_t nl = uint32_t(__popcll(bl)), nr = uint32_t(__popcll(br));
         if (COUNT) {
             ++c_node;
-            c_lchild += nl + nr;
+            c_lchild += __popcll(bl) + __popcll(br);
         }
-        if (nl * nr != 0) {
+        if (bl != 0 && br != 0) {
             // both entered: the child most of the lanes reach first goes first
             const uint32_t np = uint32_t(__popcll(bl & (~br | wave_ballot(ln <= rn))));
             const bool lfirst = 2 * np >= uint32_t(__popcll(bl | br));
@@ -515,8 +514,8 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
             stackv = (lane == sp) ? (lfirst ? right : left) : stackv;
             ++sp;
             node = lfirst ? left : right;
-        } else if (nl + nr != 0) {
-            node = nl != 0 ? left : right;
+        } else if ((bl | br) != 0) {
+            node = bl != 0 ? left : right;
         } else if (sp == 0) {
             return kDone;
         } else {
