@@ -1,5 +1,6 @@
-"""Triangle mesh for the mixed mesh + Gaussian workload: a subdivided plane and
-an icosphere. Pure geometry generation (float32 vertices, int32 indices)."""
+"""Triangle meshes for the mixed mesh + Gaussian workloads: a subdivided plane,
+an icosphere and a box (outward winding: e1 x e2 points out of closed
+shapes). Pure geometry generation (float32 vertices, int32 indices)."""
 
 from dataclasses import dataclass
 
@@ -10,7 +11,7 @@ import numpy as np
 class Mesh:
     verts: np.ndarray   # [V, 3] float32
     tris: np.ndarray    # [T, 3] int32
-    mirror: np.ndarray  # [T] int32, 1 = mirror material, 0 = diffuse
+    mirror: np.ndarray  # [T] int32 material code: 0 diffuse, 1 mirror, 2 glass
 
     @property
     def n_tris(self) -> int:
@@ -72,3 +73,29 @@ def mirror_mesh(plane_cells=50, plane_half=3.0, sphere_subdiv=4, sphere_radius=0
     mirror = np.concatenate([np.ones(len(pt), np.int32), np.zeros(len(st), np.int32)])
     return Mesh(np.ascontiguousarray(verts.astype(np.float32)), np.ascontiguousarray(tris.astype(np.int32)),
                 np.ascontiguousarray(mirror))
+
+
+def box(lo, hi):
+    """Axis-aligned box as 12 triangles, normals pointing out."""
+    lo, hi = np.asarray(lo, np.float64), np.asarray(hi, np.float64)
+    c = np.array([[x, y, z] for z in (0, 1) for y in (0, 1) for x in (0, 1)], np.float64)
+    verts = lo + c * (hi - lo)
+    # quads (a, b, c, d) counter-clockwise seen from outside
+    quads = [(0, 2, 3, 1), (4, 5, 7, 6), (0, 1, 5, 4), (2, 6, 7, 3), (0, 4, 6, 2), (1, 3, 7, 5)]
+    tris = []
+    for a, b, cc, d in quads:
+        tris += [(a, b, cc), (a, cc, d)]
+    return verts, np.asarray(tris, dtype=np.int64)
+
+
+def glass_mesh(plane_cells=50, plane_half=3.0, sphere_subdiv=4, sphere_radius=0.6, sphere_centre=(0.0, 0.0, 0.8),
+               box_lo=(0.9, -1.6, 0.05), box_hi=(1.7, -0.8, 0.85)):
+    """Mirror plane at z = 0, a glass icosphere and a glass box."""
+    pv, pt = subdivided_plane(plane_cells, plane_half)
+    sv, st = icosphere(sphere_subdiv, sphere_radius, sphere_centre)
+    bv, bt = box(box_lo, box_hi)
+    verts = np.concatenate([pv, sv, bv])
+    tris = np.concatenate([pt, st + len(pv), bt + len(pv) + len(sv)])
+    mat = np.concatenate([np.ones(len(pt), np.int32), np.full(len(st), 2, np.int32), np.full(len(bt), 2, np.int32)])
+    return Mesh(np.ascontiguousarray(verts.astype(np.float32)), np.ascontiguousarray(tris.astype(np.int32)),
+                np.ascontiguousarray(mat))
