@@ -1,13 +1,13 @@
 """Benchmark of the ray-traced Gaussian renderer on one MI355X.
 
 A step is one pass of the whole hot path over one workload: BVH rebuild
-(preprocess, Morton codes, radix sort, Karras link, refit), forward render,
+(preprocess, Morton codes, radix sort, leaf boxes, PLOC clustering), forward render,
 an L1 loss against a fixed target image, and the adjoint render producing
 gradients for all five parameter groups. Inputs are resident in HBM before the
 timed region. The default workload is the scene-scale one (1M Gaussians, one
 1920x1080 view); --workload 3 (8 views) also times one launch per view against
 the batched launch, --workload 5 runs the mesh path (reflection and shadow
-rays).
+rays), --workload 6 the three-bounce path with glass and a mirror.
 
 The launch shape (hit-buffer size, grid form, packet tile) is autotuned on the
 workload before timing unless --no-autotune; the timed steps replay a HIP
@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", type=int, default=4, choices=(1, 2, 3, 4, 5))
+    ap.add_argument("--workload", type=int, default=4, choices=(1, 2, 3, 4, 5, 6))
     ap.add_argument("--kbuf", type=int, default=0, help="fixed hit-buffer size (implies --no-autotune)")
     ap.add_argument("--persistent", action="store_true", help="persistent grid (implies --no-autotune)")
     ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
@@ -108,8 +108,8 @@ def main():
         dm = R.Mesh(t(mesh_np.verts), t(mesh_np.tris), t(mesh_np.mirror))
         mbvh = R.build_mesh_bvh(dm)
         L = w["light"]
-        shading = R.Shading(light=(float(L[0]), float(L[1]), float(L[2])))
-    frame = R.mesh_frame(nr, base) if mesh_np is not None else None
+        shading = R.Shading(light=(float(L[0]), float(L[1]), float(L[2])), max_bounces=int(w.get("bounces", 1)))
+    frame = R.mesh_frame(nr, base, shading=shading) if mesh_np is not None else None
 
     def render(bvh, gs, p, out, state=None):
         if mesh_np is not None:
@@ -331,7 +331,8 @@ def main():
             osh = OM.Shading(light=tuple(float(np.float32(x)) for x in shading.light),
                              intensity=f32(shading.intensity), albedo=f32(shading.albedo),
                              mirror_reflectance=f32(shading.mirror_reflectance),
-                             mirror_diffuse=f32(shading.mirror_diffuse), offset=f32(shading.offset))
+                             mirror_diffuse=f32(shading.mirror_diffuse), offset=f32(shading.offset),
+                             max_bounces=shading.max_bounces, ior=f32(shading.ior))
             ofwd = lambda s: OM.mesh_forward(sc, mesh_np, osh, o[s], d[s], op)
         if args.parity_rays > 0:
             sel = np.sort(rng.choice(nr, args.parity_rays, replace=False))
@@ -382,6 +383,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
                    "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
+                   "mesh_bounces": shading.max_bounces if shading is not None else 0,
                    "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None, "hit_list": base.hit_list,
                    "gradient": f"paper (eps2 {args.eps2:g})" if args.paper_gradient else "exact",
                    "loss": "mean L1" if args.loss == "l1" else "0.8 L2 + 0.2 D-SSIM (11x11, sigma 1.5)",

@@ -232,29 +232,40 @@ int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, c
                 rs_tune *result, void *stream);
 
 /* ------------------------------------------------------ mesh + Gaussians */
-/* The paper combines triangle meshes with Gaussians for mirror reflections
- * and shadows (Sec. 1, Figs. 1 and 3-6) without giving a shading model. This
- * library implements the following one:
- *   primary ray: closest triangle hit t_m (Moller-Trumbore, both faces,
- *     t > 0); Gaussians with t1 < t_m composite to (C_p, T_p); without a
- *     triangle hit the pixel is C_p + T_p * bg.
- *   at a hit P with unit normal n facing the ray and unit light direction l:
- *     mirror triangles weigh a reflection by mirror_reflectance and a diffuse
- *     term by mirror_diffuse; other triangles are diffuse (weight 1).
- *   reflection ray from P + offset*n along d - 2 (d.n) n: Gaussians up to
- *     its own closest triangle hit; background bg if it hits none, black if it
- *     does (one bounce): C_r.
- *   shadow ray from P + offset*n to the light: 0 if a triangle blocks it,
- *     else the transmittance T_s of the Gaussians on the segment.
- *   pixel = C_p + T_p (w_m C_r + w_d * albedo * max(0, n.l) * intensity * T_s).
+/* The paper combines triangle meshes with Gaussians for mirror reflections,
+ * shadows and glass (Sec. 1, Figs. 1 and 3-6) without giving a shading model.
+ * This library implements the following one. A pixel follows a chain of up
+ * to B + 1 path rays, B = max_bounces (1..RS_MAX_BOUNCES); path ray 0 is the
+ * camera ray. Path ray k (origin o, unit direction d):
+ *   closest triangle hit t_k (Moller-Trumbore, both faces, t > 0); the
+ *     Gaussians with t1 < t_k composite to (C_k, T_k) over black when it hits
+ *     a triangle, over bg when it hits none.
+ *   at a hit P with k < B, unit geometric normal n_g (e1 x e2 of the vertex
+ *   order), n = n_g turned to face the ray, unit light direction l:
+ *     diffuse (material 0): diffuse weight 1, no continuation;
+ *     mirror (1): diffuse weight mirror_diffuse; continuation from
+ *       P + offset*n along d - 2 (d.n) n with weight mirror_reflectance;
+ *     glass (2): no diffuse term; eta = 1/ior entering (d.n_g < 0), ior
+ *       leaving; cos_i = -d.n, k = 1 - eta^2 (1 - cos_i^2); k < 0: total
+ *       internal reflection (from P + offset*n, weight 1), else refraction
+ *       from P - offset*n along eta d + (eta cos_i - sqrt(k)) n with weight
+ *       1 - F, F = R0 + (1 - R0)(1 - c)^5 (Schlick), R0 = ((1-ior)/(1+ior))^2,
+ *       c = cos_i entering, sqrt(k) leaving; the reflected part is not traced.
+ *   shadow ray from P + offset*n to the light (diffuse weight > 0, n.l > 0):
+ *     0 if a triangle blocks it, else the Gaussians' transmittance T_s.
+ *   R_k = C_k + T_k (w_d albedo max(0, n.l) intensity T_s + w R_{k+1}) at a
+ *   hit with k < B, R_k = C_k otherwise (a hit of path ray B is black);
+ *   pixel = R_0. B = 1 gives primary, mirror reflection and shadow rays.
+ * Material codes outside 0..2 shade as diffuse. Spawned rays are float32.
  * The K_max / eps1 rules apply to every ray. Gradients flow through the
- * Gaussian hits of all three rays. */
+ * Gaussian hits of every ray. */
+#define RS_MAX_BOUNCES 3
 typedef struct {
     int64_t n_verts, n_tris;
     const float *verts;      /* device [n_verts][3] */
     const int32_t *tris;     /* device [n_tris][3] vertex indices (out-of-range indices
                                 set RS_ERR_NONFINITE and read vertex 0) */
-    const int32_t *material; /* device [n_tris]: 1 mirror, 0 diffuse; NULL = all diffuse */
+    const int32_t *material; /* device [n_tris]: 0 diffuse, 1 mirror, 2 glass; NULL = all diffuse */
 } rs_mesh;
 
 typedef struct {
@@ -263,9 +274,12 @@ typedef struct {
     float mirror_reflectance; /* reflection weight of mirror triangles */
     float mirror_diffuse;     /* diffuse weight of mirror triangles */
     float offset;             /* secondary-ray origin offset along the normal */
+    int32_t max_bounces;      /* B: specular continuations along a pixel's chain, 1..RS_MAX_BOUNCES */
+    float ior;                /* index of refraction of glass triangles, > 0 */
 } rs_shading;
 
-/* light (2,-2,5), intensity 1, albedo 0.8, mirror weights 0.8 / 0.2, offset 1e-4 */
+/* light (2,-2,5), intensity 1, albedo 0.8, mirror weights 0.8 / 0.2, offset
+ * 1e-4, one bounce, ior 1.5 */
 void rs_default_shading(rs_shading *s);
 
 /* Build a triangle BVH (the PLOC builder over triangle centroids) in a
@@ -279,16 +293,18 @@ int rs_build_mesh_bvh(const rs_mesh *m, void *ws, size_t ws_bytes, rs_bvh *out, 
 int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_limit, int any_hit, float *t_hit,
                   int32_t *tri, void *stream);
 
-/* Per-frame device scratch of the mesh render for n rays (secondary rays,
- * their states, the terms the adjoint needs and, with p->hit_list = C > 0,
- * the stored hit lists of the three ray sets: 3 (C + 1) 4 bytes per ray),
- * 256-byte aligned. p may be NULL (C = 0). */
-size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p);
+/* Per-frame device scratch of the mesh render for n rays (the path and shadow
+ * rays of every level, their states, the terms the adjoint needs and, with
+ * p->hit_list = C > 0, the stored hit lists of the 2B + 1 ray sets:
+ * (2B + 1)(C + 1) 4 bytes per ray), 256-byte aligned. p may be NULL (C = 0);
+ * sh may be NULL (B = 1). */
+size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p, const rs_shading *sh);
 
-/* Forward render of Gaussians + mesh with reflection and shadow rays. After
- * the triangle traces, the Gaussians along the primary, reflection and shadow
- * rays of all pixels are rendered in one persistent launch (three ray sets,
- * one packet queue). `frame` must be kept for rs_render_mesh_bwd. */
+/* Forward render of Gaussians + mesh with path and shadow rays. After the
+ * triangle traces of every level, the Gaussians along all path and shadow
+ * rays of all pixels are rendered in one persistent launch (2B + 1 ray sets,
+ * one packet queue). `frame` (rs_mesh_frame_bytes(n, p, sh)) must be kept for
+ * rs_render_mesh_bwd. */
 int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
                        const rs_shading *sh, const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame,
                        void *stream);

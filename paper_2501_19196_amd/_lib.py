@@ -25,6 +25,7 @@ RS_ZERO_COLOUR = 1 << 2
 RS_COUNTERS = 1 << 3
 RS_PAPER_GRADIENT = 1 << 4
 RS_BUILD_LBVH = 1 << 5
+RS_MAX_BOUNCES = 3
 RS_MAX_VIEWS = 64
 
 # Every symbol include/raysplats.h declares.
@@ -71,7 +72,8 @@ class rs_mesh(C.Structure):
 
 class rs_shading(C.Structure):
     _fields_ = [("light", C.c_float * 3), ("intensity", C.c_float), ("albedo", C.c_float),
-                ("mirror_reflectance", C.c_float), ("mirror_diffuse", C.c_float), ("offset", C.c_float)]
+                ("mirror_reflectance", C.c_float), ("mirror_diffuse", C.c_float), ("offset", C.c_float),
+                ("max_bounces", C.c_int32), ("ior", C.c_float)]
 
 
 class rs_tune(C.Structure):
@@ -129,7 +131,7 @@ def lib():
     L.rs_build_mesh_bvh.restype = C.c_int
     L.rs_trace_mesh.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_rays), P, C.c_int, P, P, P]
     L.rs_trace_mesh.restype = C.c_int
-    L.rs_mesh_frame_bytes.argtypes = [C.c_int64, C.POINTER(rs_params)]
+    L.rs_mesh_frame_bytes.argtypes = [C.c_int64, C.POINTER(rs_params), C.POINTER(rs_shading)]
     L.rs_mesh_frame_bytes.restype = C.c_size_t
     L.rs_render_mesh_fwd.argtypes = [C.POINTER(rs_bvh), C.POINTER(rs_bvh), C.POINTER(rs_gaussians), C.POINTER(rs_mesh),
                                      C.POINTER(rs_shading), C.POINTER(rs_rays), C.POINTER(rs_params), P, P, P]

@@ -160,10 +160,11 @@ static int check_shading(const rs_shading *sh)
 {
     if (!sh) return RS_ERR_INVALID_ARG;
     const float v[9] = {sh->light[0], sh->light[1], sh->light[2], sh->intensity, sh->albedo, sh->mirror_reflectance,
-                        sh->mirror_diffuse, sh->offset, 0.0f};
+                        sh->mirror_diffuse, sh->offset, sh->ior};
     for (float x : v)
         if (!(x == x) || x == __builtin_huge_valf() || x == -__builtin_huge_valf()) return RS_ERR_INVALID_ARG;
     if (sh->offset < 0.0f || sh->mirror_reflectance < 0.0f || sh->mirror_diffuse < 0.0f) return RS_ERR_INVALID_ARG;
+    if (sh->max_bounces < 1 || sh->max_bounces > RS_MAX_BOUNCES || !(sh->ior > 0.0f)) return RS_ERR_INVALID_ARG;
     return RS_OK;
 }
 
@@ -178,6 +179,8 @@ void rs_default_shading(rs_shading *s)
     s->mirror_reflectance = 0.8f;
     s->mirror_diffuse = 0.2f;
     s->offset = 1e-4f;
+    s->max_bounces = 1;
+    s->ior = 1.5f;
 }
 
 int rs_build_mesh_bvh(const rs_mesh *m, void *ws, size_t ws_bytes, rs_bvh *out, void *stream)
@@ -213,9 +216,10 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
                              static_cast<hipStream_t>(stream));
 }
 
-size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p)
+size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p, const rs_shading *sh)
 {
-    return n_rays >= 0 ? mesh_frame_bytes(n_rays, p && p->hit_list > 0 ? p->hit_list : 0) : 0;
+    const int b = sh && sh->max_bounces >= 1 && sh->max_bounces <= RS_MAX_BOUNCES ? sh->max_bounces : 1;
+    return n_rays >= 0 ? mesh_frame_bytes(n_rays, p && p->hit_list > 0 ? p->hit_list : 0, b) : 0;
 }
 
 int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs_gaussians *g, const rs_mesh *m,
@@ -252,7 +256,7 @@ int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
     if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
     if (!out) return RS_ERR_INVALID_ARG;
     if (rays->n > 0 && (!grad_rgb || !frame || !aligned(frame, 256))) return RS_ERR_INVALID_ARG;
-    return launch_mesh_bwd(G, g, rays, p, grad_rgb, frame, out, static_cast<hipStream_t>(stream));
+    return launch_mesh_bwd(G, g, sh, rays, p, grad_rgb, frame, out, static_cast<hipStream_t>(stream));
 }
 
 int rs_read_status(const rs_bvh *bvh, void *stream)

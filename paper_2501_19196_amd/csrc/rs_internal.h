@@ -11,7 +11,7 @@ namespace rs {
 
 constexpr uint64_t kMagic = 0x5253425648495031ull;  // "RSBVHIP1"
 constexpr int kWave = 64;
-constexpr int kMaxSets = 3;  // ray sets one render launch can carry
+constexpr int kMaxSets = 2 * RS_MAX_BOUNCES + 1;  // ray sets one render launch can carry (mesh path + shadow rays)
 constexpr int kXcdQueues = 8;  // persistent packet queues (one per XCD of MI355X)
 constexpr int kStripTiles = 16;  // persistent packet order: strips 16 tiles wide
 
@@ -203,13 +203,13 @@ void zero_gacc(const BvhDesc &D, hipStream_t st);
 int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st);
 int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, int tile_shift, float *t_hit,
                       int32_t *tri, hipStream_t st);
-size_t mesh_frame_bytes(int64_t n, int32_t cap);
+size_t mesh_frame_bytes(int64_t n, int32_t cap, int bounces);
 size_t loss_workspace_bytes(int32_t w, int32_t h);
 int launch_loss(const float *img, const float *tgt, int32_t w, int32_t h, const rs_loss_params *lp, float *loss,
                 float *grad, void *ws, hipStream_t st);
 int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,
                     const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame, hipStream_t st);
-int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
+int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *sh, const rs_rays *rays, const rs_params *p,
                     const float *grad, void *frame, const rs_grads *grads, hipStream_t st);
 void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st);
 

@@ -1,9 +1,10 @@
 // Triangle mesh + Gaussians: triangle BVH traversal (closest or any hit,
-// Moller-Trumbore), secondary-ray spawning, and the forward / adjoint
-// orchestration of the mirror + shadow shading model declared in
-// raysplats.h. The paper shows meshes with reflections and shadows in a
-// Gaussian scene (Sec. 1, Figs. 1 and 3-6) but specifies no shading model;
-// the one implemented here is stated in the header.
+// Moller-Trumbore), spawning of the path and shadow rays of every level, and
+// the forward / adjoint orchestration of the diffuse + mirror + glass shading
+// model declared in raysplats.h. The paper shows meshes with reflections,
+// shadows and glass in a Gaussian scene (Sec. 1, Figs. 1 and 3-6) but
+// specifies no shading model; the one implemented here is stated in the
+// header.
 #include <math.h>
 #include <string.h>
 
@@ -140,33 +141,44 @@ __global__ __launch_bounds__(64) void k_mesh_trace(const float4 *__restrict__ re
     }
 }
 
-// Frame scratch layout (per ray): see frame_layout.
+// Frame scratch: per level k, the path rays (level 0: the caller's rays) and
+// the shadow rays of their hits. Inactive rays carry t_max = -inf.
+struct PathLevel {
+    float *o, *d;        // [n][3] rays (level >= 1)
+    float *tmax, *bg;    // [n] Gaussian range, [n][3] background of the forward render
+    float *out;          // [n][3] C_k (+ T_k bg when the ray leaves the mesh)
+    float4 *st, *stb;    // forward state; adjoint state (radiance R_k, T_k)
+    float *t;            // [n] closest triangle distance
+    int32_t *tri;        // [n] closest triangle (-1 none)
+    float *w;            // [n] continuation weight (0: none)
+    float *shade;        // [n][3] background of the adjoint: D_k + w R_{k+1} at a hit, bg_k otherwise
+    float *g;            // [n][3] upstream gradient (level >= 1)
+    float *W;            // [n] path weight
+    int32_t *cnt, *ids;  // stored hit lists
+};
+
+struct ShadowLevel {
+    float *o, *d, *tmax;  // rays to the light (t_max = distance)
+    float *out;           // [n][3] transmittance in channel 0
+    float4 *st;
+    float *wd;            // [n] diffuse weight * albedo * (n.l) * intensity (0 when blocked or absent)
+    float *tb;            // [n] blocker distance (any hit)
+    int32_t *trib;        // [n] blocker (-1 none)
+    float *g;             // [n][3] upstream gradient of the transmittance (channel 0)
+    int32_t *cnt, *ids;
+};
+
 struct Frame {
-    float *t_mesh;   // [n]
-    int32_t *tri;    // [n]
-    int32_t *tri2;   // [n] secondary trace results
-    float *tmax_p;   // [n]
-    float *bg_p;     // [n][3]
-    float *out_p;    // [n][3]
-    float4 *st_p;    // [n]
-    float *r_o, *r_d, *r_tmax, *r_bg, *out_r;  // reflection rays
-    float4 *st_r;
-    float *s_o, *s_d, *s_tmax, *out_s;  // shadow rays
-    float4 *st_s;
-    float *t2;       // [n] secondary trace distances
-    float *w_m;      // [n] reflection weight of the hit triangle
-    float *w_s;      // [n] diffuse weight * albedo * (n.l) * intensity (0 when blocked)
-    float *shade;    // [n][3] background of the primary adjoint
-    float4 *st_pb;   // [n] primary state with the final colour
-    float *g_r, *g_s;  // [n][3] upstream gradients of the secondary rays
-    int32_t *cnt[3];   // stored hit lists of the three ray sets (hit_list > 0)
-    int32_t *ids[3];   // [cap][n] each
+    PathLevel P[RS_MAX_BOUNCES + 1];
+    ShadowLevel S[RS_MAX_BOUNCES];
+    int32_t bounces;
     size_t total;
 };
 
-static Frame frame_layout(char *base, int64_t n, int32_t cap)
+static Frame frame_layout(char *base, int64_t n, int32_t cap, int bounces)
 {
     Frame F{};
+    F.bounces = bounces;
     size_t off = 0;
     auto take = [&](size_t bytes) {
         char *p = base ? base + off : nullptr;
@@ -174,176 +186,244 @@ static Frame frame_layout(char *base, int64_t n, int32_t cap)
         return p;
     };
     const size_t f = size_t(n > 0 ? n : 1) * 4;
-    F.t_mesh = reinterpret_cast<float *>(take(f));
-    F.tri = reinterpret_cast<int32_t *>(take(f));
-    F.tri2 = reinterpret_cast<int32_t *>(take(f));
-    F.tmax_p = reinterpret_cast<float *>(take(f));
-    F.bg_p = reinterpret_cast<float *>(take(3 * f));
-    F.out_p = reinterpret_cast<float *>(take(3 * f));
-    F.st_p = reinterpret_cast<float4 *>(take(4 * f));
-    F.r_o = reinterpret_cast<float *>(take(3 * f));
-    F.r_d = reinterpret_cast<float *>(take(3 * f));
-    F.r_tmax = reinterpret_cast<float *>(take(f));
-    F.r_bg = reinterpret_cast<float *>(take(3 * f));
-    F.out_r = reinterpret_cast<float *>(take(3 * f));
-    F.st_r = reinterpret_cast<float4 *>(take(4 * f));
-    F.s_o = reinterpret_cast<float *>(take(3 * f));
-    F.s_d = reinterpret_cast<float *>(take(3 * f));
-    F.s_tmax = reinterpret_cast<float *>(take(f));
-    F.out_s = reinterpret_cast<float *>(take(3 * f));
-    F.st_s = reinterpret_cast<float4 *>(take(4 * f));
-    F.t2 = reinterpret_cast<float *>(take(f));
-    F.w_m = reinterpret_cast<float *>(take(f));
-    F.w_s = reinterpret_cast<float *>(take(f));
-    F.shade = reinterpret_cast<float *>(take(3 * f));
-    F.st_pb = reinterpret_cast<float4 *>(take(4 * f));
-    F.g_r = reinterpret_cast<float *>(take(3 * f));
-    F.g_s = reinterpret_cast<float *>(take(3 * f));
-    for (int k = 0; k < 3; ++k) {
-        F.cnt[k] = cap > 0 ? reinterpret_cast<int32_t *>(take(f)) : nullptr;
-        F.ids[k] = cap > 0 ? reinterpret_cast<int32_t *>(take(f * size_t(cap))) : nullptr;
+    auto fl = [&](size_t k) { return reinterpret_cast<float *>(take(k * f)); };
+    for (int k = 0; k <= bounces; ++k) {
+        PathLevel &L = F.P[k];
+        if (k > 0) {
+            L.o = fl(3);
+            L.d = fl(3);
+            L.g = fl(3);
+        }
+        L.tmax = fl(1);
+        L.bg = fl(3);
+        L.out = fl(3);
+        L.st = reinterpret_cast<float4 *>(fl(4));
+        L.stb = reinterpret_cast<float4 *>(fl(4));
+        L.t = fl(1);
+        L.tri = reinterpret_cast<int32_t *>(fl(1));
+        L.w = fl(1);
+        L.shade = fl(3);
+        L.W = fl(1);
+        if (cap > 0) {
+            L.cnt = reinterpret_cast<int32_t *>(fl(1));
+            L.ids = reinterpret_cast<int32_t *>(fl(size_t(cap)));
+        }
+    }
+    for (int k = 0; k < bounces; ++k) {
+        ShadowLevel &S = F.S[k];
+        S.o = fl(3);
+        S.d = fl(3);
+        S.tmax = fl(1);
+        S.out = fl(3);
+        S.st = reinterpret_cast<float4 *>(fl(4));
+        S.wd = fl(1);
+        S.tb = fl(1);
+        S.trib = reinterpret_cast<int32_t *>(fl(1));
+        S.g = fl(3);
+        if (cap > 0) {
+            S.cnt = reinterpret_cast<int32_t *>(fl(1));
+            S.ids = reinterpret_cast<int32_t *>(fl(size_t(cap)));
+        }
     }
     F.total = off;
     return F;
 }
 
 struct ShadeConst {
-    float lx, ly, lz, intensity, albedo, wm, wd, offset;
+    float lx, ly, lz, intensity, albedo, wm, wd, offset, ior;
     float bg[3];
 };
 
-// Primary rays: Gaussians are bounded by the closest triangle; a ray that hits a
-// triangle composites over a black background (its shade is added later).
-__global__ void k_mesh_primary_prep(const Frame F, int64_t n, ShadeConst C)
+constexpr int32_t kMatMirror = 1, kMatGlass = 2;
+
+// Level 0: every camera ray is active.
+__global__ void k_path_init(const PathLevel L, int64_t n)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const bool hit = F.tri[i] >= 0;
-    F.tmax_p[i] = hit ? F.t_mesh[i] : kInf;
-    for (int c = 0; c < 3; ++c) F.bg_p[3 * i + c] = hit ? 0.0f : C.bg[c];
+    L.tmax[i] = kInf;
 }
 
-// Reflection and shadow rays of every primary ray that hit a triangle; the
-// others get t_max = -inf (no work).
-__global__ void k_mesh_spawn(const float *__restrict__ origin, const float *__restrict__ dir,
-                             const float4 *__restrict__ trecords, const int32_t *__restrict__ tinv, const Frame F,
-                             int64_t n, ShadeConst C)
+// After a level's closest-hit trace: the Gaussians of an active ray stop at
+// its triangle (over black) or run to infinity (over bg).
+__global__ void k_path_prep(const PathLevel L, int64_t n, ShadeConst C)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const int32_t tri = F.tri[i];
-    F.r_tmax[i] = -kInf;
-    F.s_tmax[i] = -kInf;
-    F.w_m[i] = 0.0f;
-    F.w_s[i] = 0.0f;
+    const bool active = L.tmax[i] > 0.0f;
+    const bool hit = active && L.tri[i] >= 0;
+    if (active) L.tmax[i] = hit ? L.t[i] : kInf;
+    for (int c = 0; c < 3; ++c) L.bg[3 * i + c] = active && !hit ? C.bg[c] : 0.0f;
+    L.w[i] = 0.0f;
+}
+
+// From the hits of path level k (rays o, d): the continuation rays of level
+// k + 1 (mirror reflection, glass refraction or total internal reflection)
+// with their weights, and the shadow rays of level k.
+__global__ void k_path_spawn(const float *__restrict__ origin, const float *__restrict__ dir, const PathLevel L,
+                             const PathLevel N, const ShadowLevel S, const float4 *__restrict__ trecords,
+                             const int32_t *__restrict__ tinv, int64_t n, ShadeConst C)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    N.tmax[i] = -kInf;
+    S.tmax[i] = -kInf;
+    S.wd[i] = 0.0f;
     for (int c = 0; c < 3; ++c) {
-        F.r_o[3 * i + c] = 0.0f;
-        F.s_o[3 * i + c] = 0.0f;
-        F.r_d[3 * i + c] = c == 2 ? 1.0f : 0.0f;
-        F.s_d[3 * i + c] = c == 2 ? 1.0f : 0.0f;
+        N.o[3 * i + c] = 0.0f;
+        S.o[3 * i + c] = 0.0f;
+        N.d[3 * i + c] = c == 2 ? 1.0f : 0.0f;
+        S.d[3 * i + c] = c == 2 ? 1.0f : 0.0f;
     }
-    if (tri < 0) return;
-    const int32_t j = tinv[tri];
+    if (!(L.tmax[i] > 0.0f) || L.tri[i] < 0) return;
+    const int32_t j = tinv[L.tri[i]];
     const float4 r0 = trecords[4 * j], r1 = trecords[4 * j + 1], r2 = trecords[4 * j + 2];
     const float e1x = r0.w, e1y = r1.x, e1z = r1.y, e2x = r1.z, e2y = r1.w, e2z = r2.x;
-    float nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
-    const float nn = 1.0f / sqrtf(nx * nx + ny * ny + nz * nz);
-    nx *= nn;
-    ny *= nn;
-    nz *= nn;
+    float gx = e1y * e2z - e1z * e2y, gy = e1z * e2x - e1x * e2z, gz = e1x * e2y - e1y * e2x;
+    const float gn = 1.0f / sqrtf(gx * gx + gy * gy + gz * gz);
+    gx *= gn;
+    gy *= gn;
+    gz *= gn;
     const float dx = dir[3 * i], dy = dir[3 * i + 1], dz = dir[3 * i + 2];
-    float dn = dx * nx + dy * ny + dz * nz;
-    if (dn > 0.0f) {
-        nx = -nx;
-        ny = -ny;
-        nz = -nz;
-        dn = -dn;
-    }
-    const float t = F.t_mesh[i];
+    const float dg = dx * gx + dy * gy + dz * gz;
+    const bool entering = !(dg > 0.0f);  // the facing normal n = -n_g when the ray runs along n_g
+    const float nx = entering ? gx : -gx, ny = entering ? gy : -gy, nz = entering ? gz : -gz;
+    const float dn = entering ? dg : -dg;  // d.n <= 0
+    const float t = L.t[i];
     const float Px = origin[3 * i] + t * dx, Py = origin[3 * i + 1] + t * dy, Pz = origin[3 * i + 2] + t * dz;
-    const bool mirror = __float_as_int(r2.y) == 1;
-    const float rho_m = mirror ? C.wm : 0.0f, rho_d = mirror ? C.wd : 1.0f;
+    const int32_t mat = __float_as_int(r2.y);
+    const float rho_d = mat == kMatMirror ? C.wd : (mat == kMatGlass ? 0.0f : 1.0f);
     const float ox = Px + C.offset * nx, oy = Py + C.offset * ny, oz = Pz + C.offset * nz;
-    if (rho_m > 0.0f) {
-        F.r_o[3 * i] = ox;
-        F.r_o[3 * i + 1] = oy;
-        F.r_o[3 * i + 2] = oz;
-        F.r_d[3 * i] = dx - 2.0f * dn * nx;
-        F.r_d[3 * i + 1] = dy - 2.0f * dn * ny;
-        F.r_d[3 * i + 2] = dz - 2.0f * dn * nz;
-        F.r_tmax[i] = kInf;
-        F.w_m[i] = rho_m;
+    // continuation
+    float w = 0.0f, cx = 0.0f, cy = 0.0f, cz = 1.0f, side = 1.0f;
+    if (mat == kMatMirror && C.wm > 0.0f) {
+        w = C.wm;
+        cx = dx - 2.0f * dn * nx;
+        cy = dy - 2.0f * dn * ny;
+        cz = dz - 2.0f * dn * nz;
+    } else if (mat == kMatGlass) {
+        const float eta = entering ? 1.0f / C.ior : C.ior;
+        const float cos_i = -dn;
+        const float k = 1.0f - eta * eta * (1.0f - cos_i * cos_i);
+        if (k < 0.0f) {
+            w = 1.0f;
+            cx = dx + 2.0f * cos_i * nx;
+            cy = dy + 2.0f * cos_i * ny;
+            cz = dz + 2.0f * cos_i * nz;
+        } else {
+            const float ks = sqrtf(k);
+            const float a = eta * cos_i - ks;
+            cx = eta * dx + a * nx;
+            cy = eta * dy + a * ny;
+            cz = eta * dz + a * nz;
+            const float q = (1.0f - C.ior) / (1.0f + C.ior);
+            const float r0f = q * q;
+            const float c = 1.0f - (entering ? cos_i : ks);
+            const float c2 = c * c;
+            const float F = r0f + (1.0f - r0f) * (c2 * c2 * c);
+            w = 1.0f - F;
+            side = -1.0f;
+        }
     }
+    if (w > 0.0f) {
+        N.o[3 * i] = Px + side * C.offset * nx;
+        N.o[3 * i + 1] = Py + side * C.offset * ny;
+        N.o[3 * i + 2] = Pz + side * C.offset * nz;
+        N.d[3 * i] = cx;
+        N.d[3 * i + 1] = cy;
+        N.d[3 * i + 2] = cz;
+        N.tmax[i] = kInf;
+        L.w[i] = w;
+    }
+    // shadow ray
     const float lx = C.lx - Px, ly = C.ly - Py, lz = C.lz - Pz;
     const float nl = (nx * lx + ny * ly + nz * lz) / sqrtf(lx * lx + ly * ly + lz * lz);
     if (rho_d > 0.0f && nl > 0.0f) {
         const float sx = C.lx - ox, sy = C.ly - oy, sz = C.lz - oz;
         const float dist = sqrtf(sx * sx + sy * sy + sz * sz);
-        F.s_o[3 * i] = ox;
-        F.s_o[3 * i + 1] = oy;
-        F.s_o[3 * i + 2] = oz;
-        F.s_d[3 * i] = sx / dist;
-        F.s_d[3 * i + 1] = sy / dist;
-        F.s_d[3 * i + 2] = sz / dist;
-        F.s_tmax[i] = dist;
-        F.w_s[i] = rho_d * C.albedo * nl * C.intensity;
+        S.o[3 * i] = ox;
+        S.o[3 * i + 1] = oy;
+        S.o[3 * i + 2] = oz;
+        S.d[3 * i] = sx / dist;
+        S.d[3 * i + 1] = sy / dist;
+        S.d[3 * i + 2] = sz / dist;
+        S.tmax[i] = dist;
+        S.wd[i] = rho_d * C.albedo * nl * C.intensity;
     }
 }
 
-// After the secondary triangle traces: a reflection ray stops at its triangle
-// (black beyond it, bg when it hits none); a blocked shadow ray does no work.
-__global__ void k_mesh_secondary_prep(const Frame F, int64_t n, ShadeConst C, const float *__restrict__ t_shadow,
-                                      const int32_t *__restrict__ tri_shadow)
+// A blocked shadow ray does no work and contributes nothing.
+__global__ void k_shadow_prep(const ShadowLevel S, int64_t n)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (F.r_tmax[i] > 0.0f) {
-        const bool hit = F.tri2[i] >= 0;
-        F.r_tmax[i] = hit ? F.t2[i] : kInf;
-        for (int c = 0; c < 3; ++c) F.r_bg[3 * i + c] = hit ? 0.0f : C.bg[c];
-    } else {
-        for (int c = 0; c < 3; ++c) F.r_bg[3 * i + c] = 0.0f;
-    }
-    if (F.s_tmax[i] > 0.0f && tri_shadow[i] >= 0) {
-        F.s_tmax[i] = -kInf;
-        F.w_s[i] = 0.0f;
+    if (S.tmax[i] > 0.0f && S.trib[i] >= 0) {
+        S.tmax[i] = -kInf;
+        S.wd[i] = 0.0f;
     }
 }
 
-// pixel = C_p + T_p * shade, shade = w_m C_r + w_d albedo (n.l) I T_s; the shade
-// is also the background of the primary ray's adjoint.
-__global__ void k_mesh_combine(const Frame F, int64_t n, ShadeConst C, float *__restrict__ out_rgb)
+// Radiance bottom-up: R_B = C_B; R_k = C_k + T_k (D_k + w_k R_{k+1}) at a hit
+// with k < B; pixel = R_0. The shade D_k + w_k R_{k+1} is the background of
+// path ray k's adjoint, and (R_k, T_k) its state.
+__global__ void k_path_combine(const Frame F, int64_t n, ShadeConst C, float *__restrict__ out_rgb)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const float4 sp = F.st_p[i];
-    const float Tp = sp.w;
-    const bool hit = F.tri[i] >= 0;
-    float o[3], sh[3];
-    for (int c = 0; c < 3; ++c) {
-        sh[c] = hit ? F.w_m[i] * F.out_r[3 * i + c] + F.w_s[i] * F.out_s[3 * i] : C.bg[c];
-        o[c] = hit ? __builtin_fmaf(Tp, sh[c], F.out_p[3 * i + c]) : F.out_p[3 * i + c];
-        out_rgb[3 * i + c] = o[c];
-        F.shade[3 * i + c] = sh[c];
+    float R[3] = {0.0f, 0.0f, 0.0f};
+    bool next = false;  // R holds an active R_{k+1}
+    for (int k = F.bounces; k >= 0; --k) {
+        const PathLevel &L = F.P[k];
+        if (!(L.tmax[i] > -kInf)) {  // not spawned
+            next = false;
+            continue;
+        }
+        const float T = L.st[i].w;
+        const bool hit = k < F.bounces && L.tri[i] >= 0;
+        float sh[3];
+        for (int c = 0; c < 3; ++c) sh[c] = L.bg[3 * i + c];
+        if (hit) {
+            const float D = F.S[k].tmax[i] > 0.0f ? F.S[k].wd[i] * F.S[k].out[3 * i] : 0.0f;
+            const float w = next ? L.w[i] : 0.0f;
+            for (int c = 0; c < 3; ++c) sh[c] = __builtin_fmaf(w, R[c], D);
+        }
+        for (int c = 0; c < 3; ++c) {
+            R[c] = hit ? __builtin_fmaf(T, sh[c], L.out[3 * i + c]) : L.out[3 * i + c];
+            L.shade[3 * i + c] = sh[c];
+        }
+        L.stb[i] = make_float4(R[0], R[1], R[2], T);
+        next = true;
     }
-    F.st_pb[i] = make_float4(o[0], o[1], o[2], Tp);
+    for (int c = 0; c < 3; ++c) out_rgb[3 * i + c] = R[c];
 }
 
-// Upstream gradients of the secondary rays: g * T_p * w_m per channel for the
-// reflection, sum(g) * T_p * w_s in channel 0 for the shadow transmittance.
-__global__ void k_mesh_bwd_prep(const Frame F, int64_t n, const float *__restrict__ grad)
+// Upstream gradients top-down: W_0 = 1, W_{k+1} = W_k T_k w_k; path ray k
+// gets W_k g, shadow ray k gets W_k T_k D-weight sum(g) on its transmittance.
+__global__ void k_path_bwd_prep(const Frame F, int64_t n, const float *__restrict__ grad)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float g0 = grad[3 * i], g1 = grad[3 * i + 1], g2 = grad[3 * i + 2];
-    const float Tp = F.st_p[i].w;
-    const float wm = Tp * F.w_m[i], ws = Tp * F.w_s[i];
-    F.g_r[3 * i] = g0 * wm;
-    F.g_r[3 * i + 1] = g1 * wm;
-    F.g_r[3 * i + 2] = g2 * wm;
-    F.g_s[3 * i] = (g0 + g1 + g2) * ws;
-    F.g_s[3 * i + 1] = 0.0f;
-    F.g_s[3 * i + 2] = 0.0f;
+    float W = 1.0f;
+    for (int k = 0; k <= F.bounces; ++k) {
+        const PathLevel &L = F.P[k];
+        const bool active = L.tmax[i] > -kInf;
+        if (!active) W = 0.0f;
+        if (k > 0) {
+            L.g[3 * i] = g0 * W;
+            L.g[3 * i + 1] = g1 * W;
+            L.g[3 * i + 2] = g2 * W;
+        }
+        const float T = active ? L.st[i].w : 0.0f;
+        if (k < F.bounces) {
+            const ShadowLevel &S = F.S[k];
+            const float ws = S.tmax[i] > 0.0f ? W * T * S.wd[i] : 0.0f;
+            S.g[3 * i] = (g0 + g1 + g2) * ws;
+            S.g[3 * i + 1] = 0.0f;
+            S.g[3 * i + 2] = 0.0f;
+            W = W * T * L.w[i];
+        }
+    }
 }
 
 // ------------------------------------------------------------------- host
@@ -374,7 +454,7 @@ int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limi
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 
-size_t mesh_frame_bytes(int64_t n, int32_t cap) { return frame_layout(nullptr, n, cap).total; }
+size_t mesh_frame_bytes(int64_t n, int32_t cap, int bounces) { return frame_layout(nullptr, n, cap, bounces).total; }
 
 static ShadeConst shade_const(const rs_shading *sh, const rs_params *p)
 {
@@ -387,6 +467,7 @@ static ShadeConst shade_const(const rs_shading *sh, const rs_params *p)
     C.wm = sh->mirror_reflectance;
     C.wd = sh->mirror_diffuse;
     C.offset = sh->offset;
+    C.ior = sh->ior;
     for (int c = 0; c < 3; ++c) C.bg[c] = p->bg[c];
     return C;
 }
@@ -402,36 +483,45 @@ static rs_rays frame_rays(const rs_rays *prim, const float *o, const float *d, c
     return r;
 }
 
-// The three ray sets of a pixel: the primary ray (Gaussians in front of the
-// mesh), its mirror reflection and its shadow ray. Spawning depends only on
-// the triangle traces, so all three render in one persistent launch.
-static void mesh_sets(const Frame &F, const rs_rays *rays, rs_rays sets_rays[3], SetDesc S[3], bool bwd,
-                      const float *grad)
+// The 2B + 1 ray sets of a pixel: path rays of levels 0..B (Gaussians up to
+// their triangle) and the shadow rays of levels 0..B-1. Spawning depends only
+// on the triangle traces, so all of them render in one persistent launch.
+static int mesh_sets(const Frame &F, const rs_rays *rays, rs_rays *sr, SetDesc *S, bool bwd, const float *grad)
 {
-    sets_rays[0] = frame_rays(rays, rays->origin, rays->dir, F.tmax_p, bwd ? F.shade : F.bg_p);
-    sets_rays[1] = frame_rays(rays, F.r_o, F.r_d, F.r_tmax, F.r_bg);
-    sets_rays[2] = frame_rays(rays, F.s_o, F.s_d, F.s_tmax, nullptr);
-    for (int k = 0; k < 3; ++k) {
-        S[k] = SetDesc{};
-        S[k].rays = &sets_rays[k];
-        S[k].count = F.cnt[k];
-        S[k].ids = F.ids[k];
+    int m = 0;
+    for (int k = 0; k <= F.bounces; ++k) {
+        const PathLevel &L = F.P[k];
+        sr[m] = frame_rays(rays, k ? L.o : rays->origin, k ? L.d : rays->dir, L.tmax, bwd ? L.shade : L.bg);
+        S[m] = SetDesc{};
+        S[m].rays = &sr[m];
+        S[m].count = L.cnt;
+        S[m].ids = L.ids;
+        if (bwd) {
+            S[m].state = L.stb;  // the ray's radiance, with the shade as background
+            S[m].grad = k ? L.g : grad;
+        } else {
+            S[m].state = L.st;
+            S[m].out_rgb = L.out;
+        }
+        ++m;
     }
-    if (bwd) {
-        S[0].state = F.st_pb;  // final colour of the pixel, with the shade as background
-        S[0].grad = grad;
-        S[1].grad = F.g_r;
-        S[2].grad = F.g_s;
-    } else {
-        S[0].out_rgb = F.out_p;
-        S[1].out_rgb = F.out_r;
-        S[2].out_rgb = F.out_s;
-        S[0].state = F.st_p;
+    for (int k = 0; k < F.bounces; ++k) {
+        const ShadowLevel &H = F.S[k];
+        sr[m] = frame_rays(rays, H.o, H.d, H.tmax, nullptr);
+        S[m] = SetDesc{};
+        S[m].rays = &sr[m];
+        S[m].count = H.cnt;
+        S[m].ids = H.ids;
+        S[m].state = H.st;
+        if (bwd)
+            S[m].grad = H.g;
+        else
+            S[m].out_rgb = H.out;
+        S[m].bg[0] = S[m].bg[1] = S[m].bg[2] = 1.0f;  // transmittance: zero colours, white background
+        S[m].zero_colour = 1;
+        ++m;
     }
-    S[1].state = F.st_r;
-    S[2].state = F.st_s;
-    S[2].bg[0] = S[2].bg[1] = S[2].bg[2] = 1.0f;  // transmittance: zero colours, white background
-    S[2].zero_colour = 1;
+    return m;
 }
 
 int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,
@@ -439,55 +529,60 @@ int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, c
 {
     const int64_t n = rays->n;
     if (n == 0) return RS_OK;
-    Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list);
+    Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list, sh->max_bounces);
     const ShadeConst C = shade_const(sh, p);
     Layout LM = make_layout(M.n);
     const int ts = tile_shift_of(p);
+    const float4 *trec = reinterpret_cast<const float4 *>(M.ws + LM.records);
+    const int32_t *tinv = reinterpret_cast<const int32_t *>(M.ws + LM.inv);
+    rs_rays sr[kMaxSets];
+    SetDesc S[kMaxSets];
+    const int nsets = mesh_sets(F, rays, sr, S, false, nullptr);
     int e;
-    // 1. triangle traces: primary closest hits, then the secondary rays they spawn
-    if ((e = launch_trace_mesh(M, rays, nullptr, 0, ts, F.t_mesh, F.tri, st))) return e;
-    k_mesh_primary_prep<<<grid_for(n), 256, 0, st>>>(F, n, C);
-    k_mesh_spawn<<<grid_for(n), 256, 0, st>>>(rays->origin, rays->dir,
-                                               reinterpret_cast<const float4 *>(M.ws + LM.records),
-                                               reinterpret_cast<const int32_t *>(M.ws + LM.inv), F, n, C);
-    rs_rays rr[3];
-    SetDesc S[3];
-    mesh_sets(F, rays, rr, S, false, nullptr);
-    if ((e = launch_trace_mesh(M, &rr[1], F.r_tmax, 0, ts, F.t2, F.tri2, st))) return e;
-    // shadow blockers: any triangle strictly before the light (results parked in out_s / g_s)
-    if ((e = launch_trace_mesh(M, &rr[2], F.s_tmax, 1, ts, F.out_s, reinterpret_cast<int32_t *>(F.g_s), st)))
-        return e;
-    k_mesh_secondary_prep<<<grid_for(n), 256, 0, st>>>(F, n, C, F.out_s, reinterpret_cast<const int32_t *>(F.g_s));
-    // 2. Gaussians along all three ray sets in one persistent launch
+    // 1. triangle traces level by level: closest hits of the path rays, spawning, shadow blockers
+    k_path_init<<<grid_for(n), 256, 0, st>>>(F.P[0], n);
+    for (int k = 0; k <= F.bounces; ++k) {
+        const PathLevel &L = F.P[k];
+        if ((e = launch_trace_mesh(M, &sr[k], L.tmax, 0, ts, L.t, L.tri, st))) return e;
+        k_path_prep<<<grid_for(n), 256, 0, st>>>(L, n, C);
+        if (k == F.bounces) break;
+        const ShadowLevel &H = F.S[k];
+        k_path_spawn<<<grid_for(n), 256, 0, st>>>(k ? L.o : rays->origin, k ? L.d : rays->dir, L, F.P[k + 1], H,
+                                                   trec, tinv, n, C);
+        // blockers: any triangle strictly before the light
+        if ((e = launch_trace_mesh(M, &sr[F.bounces + 1 + k], H.tmax, 1, ts, H.tb, H.trib, st))) return e;
+        k_shadow_prep<<<grid_for(n), 256, 0, st>>>(H, n);
+    }
+    // 2. Gaussians along all ray sets in one persistent launch
     rs_params ps = *p;
     ps.flags |= RS_PERSISTENT;
-    if ((e = launch_sets(G, g, &ps, 3, S, false, st))) return e;
-    // 3. combine
-    k_mesh_combine<<<grid_for(n), 256, 0, st>>>(F, n, C, out_rgb);
+    if ((e = launch_sets(G, g, &ps, nsets, S, false, st))) return e;
+    // 3. combine bottom-up
+    k_path_combine<<<grid_for(n), 256, 0, st>>>(F, n, C, out_rgb);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 
-int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
-                    const float *grad, void *frame, const rs_grads *grads, hipStream_t st)
+int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *sh, const rs_rays *rays,
+                    const rs_params *p, const float *grad, void *frame, const rs_grads *grads, hipStream_t st)
 {
     const int64_t n = rays->n;
     zero_gacc(G, st);
     if (n > 0) {
-        Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list);
-        k_mesh_bwd_prep<<<grid_for(n), 256, 0, st>>>(F, n, grad);
-        rs_rays rr[3];
-        SetDesc S[3];
-        mesh_sets(F, rays, rr, S, true, grad);
+        Frame F = frame_layout(static_cast<char *>(frame), n, p->hit_list, sh->max_bounces);
+        k_path_bwd_prep<<<grid_for(n), 256, 0, st>>>(F, n, grad);
+        rs_rays sr[kMaxSets];
+        SetDesc S[kMaxSets];
+        const int nsets = mesh_sets(F, rays, sr, S, true, grad);
         rs_params ps = *p;
         ps.flags |= RS_PERSISTENT;
         int e;
         if (p->hit_list > 0) {
-            // stored lists of all three sets, then traversal for the rays whose list overflowed
-            if ((e = launch_sets(G, g, &ps, 3, S, true, st, true))) return e;
+            // stored lists of all sets, then traversal for the rays whose list overflowed
+            if ((e = launch_sets(G, g, &ps, nsets, S, true, st, true))) return e;
             if (p->max_hits == 0 || p->max_hits > p->hit_list)
-                if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
+                if ((e = launch_sets(G, g, &ps, nsets, S, true, st))) return e;
         } else {
-            if ((e = launch_sets(G, g, &ps, 3, S, true, st))) return e;
+            if ((e = launch_sets(G, g, &ps, nsets, S, true, st))) return e;
         }
     }
     scatter_gacc(G, grads, st);

@@ -351,7 +351,8 @@ template <typename PT>
 __device__ inline LaneRay lane_ray(const PT &P, const Ptrs &ptr, int64_t pkt, int lane)
 {
     LaneRay L;
-    L.si = (pkt >= P.packets_per_set ? 1 : 0) + (pkt >= 2 * P.packets_per_set ? 1 : 0);
+    L.si = 0;
+    while (L.si + 1 < kMaxSets && pkt >= int64_t(L.si + 1) * P.packets_per_set) ++L.si;
     const RaySet &S = ptr.set[L.si];
     const int64_t local = pkt - L.si * P.packets_per_set;
     L.id = packet_ray(P, P.persistent ? strip_major_packet(P, local, P.strip_tiles) : local, lane, L.valid);

@@ -250,7 +250,7 @@ def download(bvh: BVH):
 class Mesh:
     verts: torch.Tensor            # [V, 3] float32
     tris: torch.Tensor             # [T, 3] int32
-    material: torch.Tensor = None  # [T] int32, 1 mirror / 0 diffuse
+    material: torch.Tensor = None  # [T] int32: 0 diffuse, 1 mirror, 2 glass
 
     def c(self):
         _dev(self.verts, "verts")
@@ -273,6 +273,8 @@ class Shading:
     mirror_reflectance: float = 0.8
     mirror_diffuse: float = 0.2
     offset: float = 1e-4
+    max_bounces: int = 1
+    ior: float = 1.5
 
     def c(self):
         s = L.rs_shading()
@@ -281,6 +283,7 @@ class Shading:
         s.intensity, s.albedo = float(self.intensity), float(self.albedo)
         s.mirror_reflectance, s.mirror_diffuse = float(self.mirror_reflectance), float(self.mirror_diffuse)
         s.offset = float(self.offset)
+        s.max_bounces, s.ior = int(self.max_bounces), float(self.ior)
         return s
 
 
@@ -306,9 +309,11 @@ def trace_mesh(mbvh: BVH, rays: Rays, t_limit=None, any_hit=False):
     return t, tri
 
 
-def mesh_frame(n, params=None, device="cuda"):
+def mesh_frame(n, params=None, device="cuda", shading=None):
     pc = params.c() if params is not None else None
-    nbytes = int(L.lib().rs_mesh_frame_bytes(int(n), C.byref(pc) if pc is not None else None))
+    sc = shading.c() if shading is not None else None
+    nbytes = int(L.lib().rs_mesh_frame_bytes(int(n), C.byref(pc) if pc is not None else None,
+                                             C.byref(sc) if sc is not None else None))
     return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
 
 
@@ -318,7 +323,7 @@ def render_mesh_fwd(gbvh: BVH, mbvh: BVH, g: Gaussians, mesh: Mesh, shading: Sha
     if out is None:
         out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
     if frame is None:
-        frame = mesh_frame(n, params, rays.origin.device)
+        frame = mesh_frame(n, params, rays.origin.device, shading)
     gc, mc, sc, rc, pc = g.c(), mesh.c(), shading.c(), rays.c(), params.c()
     L.check(L.lib().rs_render_mesh_fwd(C.byref(gbvh.desc), C.byref(mbvh.desc), C.byref(gc), C.byref(mc), C.byref(sc),
                                        C.byref(rc), C.byref(pc), _ptr(out), _ptr(frame), _stream()),

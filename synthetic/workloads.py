@@ -6,7 +6,7 @@ Each entry builds lazily because the large scenes take a few seconds to draw.
 import numpy as np
 
 from . import scenes, cameras
-from .mesh import mirror_mesh
+from .mesh import glass_mesh, mirror_mesh
 
 
 def _w1():
@@ -42,7 +42,14 @@ def _w5():
                 light=np.array([2.0, -2.0, 5.0]))
 
 
-WORKLOADS = {1: _w1, 2: _w2, 3: _w3, 4: _w4, 5: _w5}
+def _w6():
+    sc = scenes.scene_config5()
+    cams = cameras.circle_cameras(4, 6.0, 3.0, (1024, 768))
+    return dict(name="glass-500k-4x1024x768", scene=sc, cams=cams, mesh=glass_mesh(), bounces=3,
+                light=np.array([2.0, -2.0, 5.0]))
+
+
+WORKLOADS = {1: _w1, 2: _w2, 3: _w3, 4: _w4, 5: _w5, 6: _w6}
 
 
 def workload(k):
