@@ -109,7 +109,7 @@ typedef struct {
 
 /* Renderer knobs. Q: ellipsoid quantile (Sec. 3; > 0). eps1: transmittance
  * threshold (>= 0). t_min: minimum hit depth (finite, >= 0). max_hits: K_max (0 = unbounded).
- * kbuf: hits gathered per ray per traversal round (8, 16, 24 or 32; 0 = 24; the
+ * kbuf: hits gathered per ray per traversal round (8, 16, 24, 32 or 48; 0 = 24; the
  * result does not depend on it).
  * stack_depth: traversal stack entries (1..64; 0 = 64). tile_width: width in
  * pixels of the 64-ray packet tile of a view (4, 8, 16 or 32, i.e. 4x16, 8x8,
@@ -220,7 +220,7 @@ typedef struct {
 } rs_tune;
 
 /* Times every candidate on the caller's own BVH, Gaussians and rays: kbuf in
- * {8, 16, 24, 32} x {one workgroup per packet, persistent queue} x tile width
+ * {8, 16, 24, 32, 48} x {one workgroup per packet, persistent queue} x tile width
  * {8, 16} (8x8 / 16x4 pixels; only 8 when the rays carry no views). Each runs
  * once untimed, then `reps` (1..100) times between hipEvents on `stream`.
  * grad_rgb (device [n][3], optional) also times the adjoint, which then

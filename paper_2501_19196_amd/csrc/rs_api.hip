@@ -21,7 +21,8 @@ static int check_params(const rs_params *p)
     if (!p) return RS_ERR_INVALID_ARG;
     if (!(p->Q > 0.0f) || !(p->eps1 >= 0.0f) || p->max_hits < 0 || !(p->t_min >= 0.0f) || !(p->t_min < 3.0e38f))
         return RS_ERR_INVALID_ARG;
-    if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32) return RS_ERR_INVALID_ARG;
+    if (p->kbuf != 0 && p->kbuf != 8 && p->kbuf != 16 && p->kbuf != 24 && p->kbuf != 32 && p->kbuf != 48)
+        return RS_ERR_INVALID_ARG;
     if (p->stack_depth < 0 || p->stack_depth > 64) return RS_ERR_INVALID_ARG;
     if (p->tile_width != 0 && p->tile_width != 4 && p->tile_width != 8 && p->tile_width != 16 && p->tile_width != 32)
         return RS_ERR_INVALID_ARG;
@@ -323,10 +324,10 @@ int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, c
         ms /= float(reps);
         return RS_OK;
     };
-    static const int kbufs[4] = {8, 16, 24, 32};
+    static const int kbufs[5] = {8, 16, 24, 32, 48};
     const int n_tiles = rays->n_views > 0 ? 2 : 1;
     int best_f = -1, best_b = -1;
-    for (int ki = 0; ki < 4 && !e; ++ki) {
+    for (int ki = 0; ki < 5 && !e; ++ki) {
         for (int pers = 0; pers < 2 && !e; ++pers) {
             for (int ti = 0; ti < n_tiles && !e; ++ti) {
                 const int c = result->n;

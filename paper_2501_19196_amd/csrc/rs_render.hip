@@ -65,9 +65,6 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
                                      float Q, float &t1, float &h2)
 {
     const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
-    const float wx = xy * ray.dz - xz * ray.dy;
-    const float wy = xz * ray.dx - xx * ray.dz;
-    const float wz = xx * ray.dy - xy * ray.dx;
     // rows of R^T
     const float a00 = r0.x, a01 = r0.y, a02 = r0.z, a10 = r0.w, a11 = r1.x, a12 = r1.y, a20 = r1.z, a21 = r1.w,
                 a22 = r2.x;
@@ -78,9 +75,10 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float e0 = a00 * ray.dx + a01 * ray.dy + a02 * ray.dz;
     const float e1 = a10 * ray.dx + a11 * ray.dy + a12 * ray.dz;
     const float e2 = a20 * ray.dx + a21 * ray.dy + a22 * ray.dz;
-    const float v0 = a00 * wx + a01 * wy + a02 * wz;
-    const float v1 = a10 * wx + a11 * wy + a12 * wz;
-    const float v2 = a20 * wx + a21 * wy + a22 * wz;
+    // R^T ((o - m) x d) = y x e: a rotation preserves cross products
+    const float v0 = y1 * e2 - y2 * e1;
+    const float v1 = y2 * e0 - y0 * e2;
+    const float v2 = y0 * e1 - y1 * e0;
     const float o0 = D0 * y0, o1 = D1 * y1, o2 = D2 * y2;
     const float d0 = D0 * e0, d1 = D1 * e1, d2 = D2 * e2;
     const float u0 = (D1 * D2) * v0, u1 = (D0 * D2) * v1, u2 = (D0 * D1) * v2;
@@ -549,8 +547,8 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 #endif
 constexpr int waves_for(int K, bool bwd)
 {
-    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : 2)))
-               : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : 3)));
+    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : (K <= 32 ? 2 : 1))))
+               : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : (K <= 32 ? 3 : 2))));
 }
 
 template <int K, bool BWD, bool BRUTE, bool COUNT>
@@ -1005,6 +1003,7 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
             case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
             case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
             case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            case 48: launch_k<48>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
             default: return RS_ERR_INVALID_ARG;
             }
         }

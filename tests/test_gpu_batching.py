@@ -82,7 +82,7 @@ def test_autotune_picks_a_listed_candidate_with_identical_output(hit_list):
     ref_g = [t.clone() for t in R.render_bwd(bvh, g, rays, p, grad, state)]
     pf, pb, rows = R.autotune(bvh, g, rays, p, grad_rgb=grad, reps=1)
     print("autotune", pf, pb, flush=True)
-    assert len(rows) == 16
+    assert len(rows) == 20
     assert all(r["ms_fwd"] > 0 and r["ms_bwd"] > 0 for r in rows)
     best_f = min(rows, key=lambda r: r["ms_fwd"])
     assert (pf.kbuf, bool(pf.flags & 2), pf.tile_width) == (best_f["kbuf"], best_f["persistent"],
@@ -96,7 +96,7 @@ def test_autotune_picks_a_listed_candidate_with_identical_output(hit_list):
     _grads_close(R.render_bwd(bvh, g, rays, pb, grad, state2), ref_g)
     # forward-only tuning leaves bwd = fwd; rays without views try one tile shape
     pf2, pb2, rows2 = R.autotune(bvh, g, G.rays_of(o, d), p, reps=1)
-    assert len(rows2) == 8 and pb2 == pf2 and all(r["ms_bwd"] == 0 for r in rows2)
+    assert len(rows2) == 10 and pb2 == pf2 and all(r["ms_bwd"] == 0 for r in rows2)
 
 
 @pytest.mark.parametrize("hit_list", [0, 128])

@@ -72,7 +72,7 @@ def test_grazing_flat_scene_brute_equals_bvh():
     _parity(sc, o, d, R.Params(), views=views, label="grazing flats")
 
 
-@pytest.mark.parametrize("kbuf", [8, 24, 32])
+@pytest.mark.parametrize("kbuf", [8, 24, 32, 48])
 def test_hit_buffer_size_does_not_change_result(kbuf):
     print("case kbuf", kbuf, flush=True)
     G, R = _g()
