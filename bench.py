@@ -401,6 +401,8 @@ def main():
                      "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": traffic,
                      "algorithmic_flops": float(dom_flops)},
         "work_per_ray": {k: round(v / nr, 2) for k, v in cf.items() if v},
+        "work_per_ray_bwd": {("list_packets" if k == "r9" else "list_composited" if k == "r10" else
+                              "list_grad_groups" if k == "r11" else k): round(v / nr, 3) for k, v in cb.items() if v},
         "autotune": tune,
         "batching": batching,
         "device_status": status,
