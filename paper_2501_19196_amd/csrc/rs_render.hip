@@ -262,30 +262,50 @@ __device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1
 }
 
 // Sum 16 per-lane values over the wavefront, transposed: after the call lane l
-// holds the wave total of value l >> 2 (exchange halves at distances 32, 16, 8
-// and 4, then fold the remaining two lane bits): 17 shuffles instead of 16 x 6.
+// holds the wave total of value l >> 2. Each stage halves the values a lane
+// carries and folds one lane bit, all in VALU cross-lane operations (no LDS):
+// bit 5 and bit 4 by the CDNA4 row swaps (v_permlane32_swap exchanges rows 2-3
+// of one register with rows 0-1 of another, v_permlane16_swap odd rows with
+// even rows; the sum of the two swapped registers is then the pair total of
+// one value in one half and of the other value in the other half), bit 3 by a
+// row rotation by 8 (partner l ^ 8), bit 2 by the half-row mirror (partner
+// l ^ 7), and the last two bits by quad permutations.
+template <int CTRL>
+__device__ inline float dpp(float v)
+{
+    return __builtin_amdgcn_update_dpp(0.0f, v, CTRL, 0xf, 0xf, false);
+}
+constexpr int kDppRowRor8 = 0x128;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
+
 __device__ inline float wave_sum16_transposed(const float (&in)[16], int lane)
 {
     float v8[8], v4[4], v2[2];
-    const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const float keep = b5 ? in[i + 8] : in[i], send = b5 ? in[i] : in[i + 8];
-        v8[i] = keep + __shfl_xor(send, 32);
+        // lanes 0-31 end with value i of lanes l and l + 32, lanes 32-63 with value i + 8
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(in[i]), __float_as_uint(in[i + 8]), false,
+                                                        false);
+        v8[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const float keep = b4 ? v8[i + 4] : v8[i], send = b4 ? v8[i] : v8[i + 4];
-        v4[i] = keep + __shfl_xor(send, 16);
+        // even rows end with value i of lanes l and l ^ 16, odd rows with value i + 4
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v8[i]), __float_as_uint(v8[i + 4]), false,
+                                                        false);
+        v4[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
     }
+    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const float keep = b3 ? v4[i + 2] : v4[i], send = b3 ? v4[i] : v4[i + 2];
-        v2[i] = keep + __shfl_xor(send, 8);
+        v2[i] = keep + dpp<kDppRowRor8>(send);
     }
-    float v = (b2 ? v2[1] : v2[0]) + __shfl_xor(b2 ? v2[0] : v2[1], 4);
-    v += __shfl_xor(v, 2);
-    v += __shfl_xor(v, 1);
+    float v = (b2 ? v2[1] : v2[0]) + dpp<kDppRowHalfMirror>(b2 ? v2[0] : v2[1]);
+    v += dpp<kDppQuadXor1>(v);
+    v += dpp<kDppQuadXor2>(v);
     return v;
 }
 
