@@ -440,9 +440,10 @@ __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, con
 }
 
 // Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation: for
-// each distinct Gaussian among the active lanes, the lanes holding it are
-// summed (transposed butterfly) and one 14-lane atomic instruction adds the
-// totals to its 64-byte accumulator line.
+// each distinct Gaussian held by several active lanes, those lanes are summed
+// (transposed butterfly) and one 14-lane atomic instruction adds the totals to
+// its 64-byte accumulator line; Gaussians held by one lane go four to an
+// atomic instruction through an LDS transpose.
 //   dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the
 //   remaining colour of the last composited hit is T_final bg, so there
 //   dC/dalpha = T_k (c_k - bg).
@@ -475,13 +476,17 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
         G.v[13] = zc ? 0.0f : Gd.gb * wgt;
     }
     const uint64_t lane_bit = 1ull << lane;
-    uint64_t todo = act_mask;
+    uint64_t todo = act_mask, single = 0;
     while (todo) {
         const int leader = __builtin_ctzll(todo);
         const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
         const uint64_t same = wave_ballot(act && gid == lg);
         todo &= ~same;
         if (COUNT) ++c_group;
+        if ((same & (same - 1)) == 0) {
+            single |= same;  // nothing to sum: transposed through LDS below
+            continue;
+        }
         const bool mine = (same & lane_bit) != 0;
         float in[16];
 #pragma unroll
@@ -490,6 +495,29 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
         in[15] = 0.0f;
         const float tot = wave_sum16_transposed(in, lane);
         if ((lane & 3) == 0 && (lane >> 2) < 14) unsafeAtomicAdd(gacc + 16 * int64_t(lg) + (lane >> 2), tot);
+    }
+    if (single) {
+        // Gaussians held by one lane: each such lane writes its 14 values and the Gaussian index to
+        // the slot of its rank, then 16-lane segments read one slot each, so one atomic instruction
+        // adds the values of four Gaussians (one 64-byte accumulator line per segment). The wave is
+        // the whole workgroup, and its LDS operations complete in order.
+        __shared__ float slots[kWave * 16];
+        if (single & lane_bit) {
+            const int rank = __popcll(single & (lane_bit - 1));
+            float *sl = slots + 16 * rank;
+#pragma unroll
+            for (int v = 0; v < 14; ++v) sl[v] = G.v[v];
+            sl[14] = __uint_as_float(gid);
+        }
+        const int ns = __popcll(single);
+        const int v = lane & 15;
+        for (int b = 0; b < ns; b += 4) {
+            const int slot = b + (lane >> 4);
+            if (slot < ns && v < 14) {
+                const uint32_t g = __float_as_uint(slots[16 * slot + 14]);
+                unsafeAtomicAdd(gacc + 16 * int64_t(g) + v, slots[16 * slot + v]);
+            }
+        }
     }
 }
 
