@@ -261,54 +261,6 @@ __device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1
     G.v[10] = dLda * __expf(-0.5f * h2);
 }
 
-// Sum 16 per-lane values over the wavefront, transposed: after the call lane l
-// holds the wave total of value l >> 2. Each stage halves the values a lane
-// carries and folds one lane bit, all in VALU cross-lane operations (no LDS):
-// bit 5 and bit 4 by the CDNA4 row swaps (v_permlane32_swap exchanges rows 2-3
-// of one register with rows 0-1 of another, v_permlane16_swap odd rows with
-// even rows; the sum of the two swapped registers is then the pair total of
-// one value in one half and of the other value in the other half), bit 3 by a
-// row rotation by 8 (partner l ^ 8), bit 2 by the half-row mirror (partner
-// l ^ 7), and the last two bits by quad permutations.
-template <int CTRL>
-__device__ inline float dpp(float v)
-{
-    return __builtin_amdgcn_update_dpp(0.0f, v, CTRL, 0xf, 0xf, false);
-}
-constexpr int kDppRowRor8 = 0x128;
-constexpr int kDppRowHalfMirror = 0x141;
-constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1, 0, 3, 2]
-constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2, 3, 0, 1]
-
-__device__ inline float wave_sum16_transposed(const float (&in)[16], int lane)
-{
-    float v8[8], v4[4], v2[2];
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        // lanes 0-31 end with value i of lanes l and l + 32, lanes 32-63 with value i + 8
-        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(in[i]), __float_as_uint(in[i + 8]), false,
-                                                        false);
-        v8[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        // even rows end with value i of lanes l and l ^ 16, odd rows with value i + 4
-        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v8[i]), __float_as_uint(v8[i + 4]), false,
-                                                        false);
-        v4[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    }
-    const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-        const float keep = b3 ? v4[i + 2] : v4[i], send = b3 ? v4[i] : v4[i + 2];
-        v2[i] = keep + dpp<kDppRowRor8>(send);
-    }
-    float v = (b2 ? v2[1] : v2[0]) + dpp<kDppRowHalfMirror>(b2 ? v2[0] : v2[1]);
-    v += dpp<kDppQuadXor1>(v);
-    v += dpp<kDppQuadXor2>(v);
-    return v;
-}
-
 // ----------------------------------------------------------------- kernel
 
 // One set of rays traced by a launch: its rays, optional per-ray limit and
@@ -439,11 +391,10 @@ __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, con
     }
 }
 
-// Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation: for
-// each distinct Gaussian held by several active lanes, those lanes are summed
-// (transposed butterfly) and one 14-lane atomic instruction adds the totals to
-// its 64-byte accumulator line; Gaussians held by one lane go four to an
-// atomic instruction through an LDS transpose.
+// Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation: the
+// active lanes' contributions are summed per distinct Gaussian through LDS and
+// one 14-lane segment of an atomic instruction adds each Gaussian's totals to
+// its 64-byte accumulator line (four Gaussians per instruction).
 //   dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the
 //   remaining colour of the last composited hit is T_final bg, so there
 //   dC/dalpha = T_k (c_k - bg).
@@ -475,48 +426,41 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
         G.v[12] = zc ? 0.0f : Gd.gg * wgt;
         G.v[13] = zc ? 0.0f : Gd.gb * wgt;
     }
+    // Lanes holding the same Gaussian form a group; groups are numbered in order and each
+    // group's lanes store their 14 values in consecutive LDS rows. Then 16-lane segments sum
+    // one group's rows each, so one atomic instruction adds the totals of four Gaussians (one
+    // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
+    // operations complete in order.
+    __shared__ float rows[kWave * 16];
+    __shared__ int4 groups[kWave];  // Gaussian index, first row, rows
     const uint64_t lane_bit = 1ull << lane;
-    uint64_t todo = act_mask, single = 0;
+    uint64_t todo = act_mask;
+    int ng = 0, pos = 0, mypos = 0;
     while (todo) {
         const int leader = __builtin_ctzll(todo);
         const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
         const uint64_t same = wave_ballot(act && gid == lg);
         todo &= ~same;
         if (COUNT) ++c_group;
-        if ((same & (same - 1)) == 0) {
-            single |= same;  // nothing to sum: transposed through LDS below
-            continue;
-        }
-        const bool mine = (same & lane_bit) != 0;
-        float in[16];
-#pragma unroll
-        for (int v = 0; v < 14; ++v) in[v] = mine ? G.v[v] : 0.0f;
-        in[14] = 0.0f;
-        in[15] = 0.0f;
-        const float tot = wave_sum16_transposed(in, lane);
-        if ((lane & 3) == 0 && (lane >> 2) < 14) unsafeAtomicAdd(gacc + 16 * int64_t(lg) + (lane >> 2), tot);
+        const int m = __popcll(same);
+        mypos = (same & lane_bit) ? pos + __popcll(same & (lane_bit - 1)) : mypos;
+        if (lane == leader) groups[ng] = make_int4(int32_t(lg), pos, m, 0);
+        ++ng;
+        pos += m;
     }
-    if (single) {
-        // Gaussians held by one lane: each such lane writes its 14 values and the Gaussian index to
-        // the slot of its rank, then 16-lane segments read one slot each, so one atomic instruction
-        // adds the values of four Gaussians (one 64-byte accumulator line per segment). The wave is
-        // the whole workgroup, and its LDS operations complete in order.
-        __shared__ float slots[kWave * 16];
-        if (single & lane_bit) {
-            const int rank = __popcll(single & (lane_bit - 1));
-            float *sl = slots + 16 * rank;
+    if (act) {
+        float *r = rows + 16 * mypos;
 #pragma unroll
-            for (int v = 0; v < 14; ++v) sl[v] = G.v[v];
-            sl[14] = __uint_as_float(gid);
-        }
-        const int ns = __popcll(single);
-        const int v = lane & 15;
-        for (int b = 0; b < ns; b += 4) {
-            const int slot = b + (lane >> 4);
-            if (slot < ns && v < 14) {
-                const uint32_t g = __float_as_uint(slots[16 * slot + 14]);
-                unsafeAtomicAdd(gacc + 16 * int64_t(g) + v, slots[16 * slot + v]);
-            }
+        for (int v = 0; v < 14; ++v) r[v] = G.v[v];
+    }
+    const int v = lane & 15;
+    for (int b = 0; b < ng; b += 4) {
+        const int gi = b + (lane >> 4);
+        if (gi < ng && v < 14) {
+            const int4 gd = groups[gi];
+            float t = rows[16 * gd.y + v];
+            for (int j = 1; j < gd.z; ++j) t += rows[16 * (gd.y + j) + v];
+            unsafeAtomicAdd(gacc + 16 * int64_t(uint32_t(gd.x)) + v, t);
         }
     }
 }
