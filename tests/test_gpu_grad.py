@@ -61,6 +61,22 @@ def test_tiny_scene_gradients():
                  views=[(0, 24, 20)], label="tiny")
 
 
+@pytest.mark.parametrize("n,hit_list", [(1, 0), (1, 64), (3, 64), (3, 0)])
+def test_one_gaussian_per_packet_gradients(n, hit_list):
+    """Large Gaussians covering the whole view: every lane of a packet holds the
+    same Gaussian at a step, the largest groups of the wave aggregation (and,
+    for n = 1, a BVH whose root is a leaf)."""
+    print("case big groups", n, hit_list, flush=True)
+    G, R = _g()
+    sc = scenes.random_scene(60 + n, n, box=0.1, scale_lo=0.8, scale_hi=1.2)
+    cam = look_at_camera((0, 0, -4), (0, 0, 0), (0, 1, 0), 16, 16, fov_y_deg=20)
+    o, d = pinhole_rays(cam)
+    rng = np.random.default_rng(2)
+    _, ref = _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), R.Params(bg=(0.1, 0.2, 0.3), hit_list=hit_list),
+                          views=[(0, 16, 16)], label="big groups")
+    assert np.linalg.norm(ref["mean"]) > 0
+
+
 def test_config1_gradients():
     print("case config1 grads", flush=True)
     G, R = _g()
