@@ -185,7 +185,7 @@ int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
 /* Adjoint render (App. A.3-A.6): replays each ray's hits front to back, from
  * its stored hit list (p->hit_list > 0) or by traversing the BVH again, and
  * accumulates d/dtheta sum_k <grad_rgb[k], C_k> into `out` with
- * wave-aggregated float32 atomics. Must use the same bvh, scene, rays and
+ * float32 atomics, aggregated per wave by Gaussian. Must use the same bvh, scene, rays and
  * params (hit_list included) as the forward call that wrote ray_state.
  * grad_rgb: device float32 [rays->n][3]. */
 int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
