@@ -290,10 +290,24 @@ struct Ptrs {
 // grids take one packet per workgroup; persistent ones first drain the queue
 // of their own XCD's chunk (a compact image region, so that XCD's L2 holds
 // its working set), then take from the other chunks.
+#ifndef RS_XCD_RUN
+#define RS_XCD_RUN 32
+#endif
+constexpr int64_t kXcdRun = RS_XCD_RUN;
+
 template <typename PT>
 __device__ inline int64_t next_packet(const PT &P, uint32_t *queue, int lane, int xcd, int &qi, int64_t &iter)
 {
-    if (!P.persistent) return iter++ > 0 ? P.n_packets : int64_t(blockIdx.x);
+    if (!P.persistent) {
+        // plain grid: workgroups are dealt to the XCDs in turn, so workgroup b runs on XCD
+        // b mod 8. Packets are dealt in runs of kXcdRun consecutive ones (a compact strip of
+        // tiles), so the waves an XCD runs at a time share fewer Gaussians in its L2, while
+        // every XCD still samples the whole image (the grid is rounded up to whole deals; the
+        // few packets beyond n_packets exit)
+        if (iter++ > 0) return P.n_packets;
+        const int64_t b = blockIdx.x, i = b / kXcdQueues;
+        return (i / kXcdRun * kXcdQueues + b % kXcdQueues) * kXcdRun + i % kXcdRun;
+    }
     while (qi < kXcdQueues) {
         const int q = (xcd + qi) & (kXcdQueues - 1);
         uint32_t p = 0;
@@ -978,7 +992,8 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
             const int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
             grid = int(waves < P.n_packets ? waves : P.n_packets);
         } else {
-            grid = int(P.n_packets);
+            const int64_t deal = int64_t(kXcdQueues) * kXcdRun;
+            grid = int((P.n_packets + deal - 1) / deal * deal);
         }
         const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
         const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
