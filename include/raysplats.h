@@ -117,9 +117,9 @@ typedef struct {
  * hit_list: store-or-recompute choice of the adjoint (0..4096; 0 = recompute):
  * with C > 0 the forward also records, per ray, the ids of the first C
  * Gaussians it composites (4 C bytes per ray of ray state) and the adjoint
- * replays those lists instead of traversing the BVH again; rays that
- * composite more than C hits are re-traversed. The gradients are the same
- * (up to float atomic order). The mesh renders keep their lists in the frame. */
+ * replays those lists instead of traversing the BVH again; a ray that
+ * composites more than C hits replays its C stored hits and traverses only for
+ * the hits after them. The gradients are the same (up to float atomic order). The mesh renders keep their lists in the frame. */
 typedef struct {
     float Q, eps1, t_min;
     int32_t max_hits;

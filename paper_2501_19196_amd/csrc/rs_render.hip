@@ -371,19 +371,20 @@ __device__ inline LaneRay lane_ray(const PT &P, const Ptrs &ptr, int64_t pkt, in
 struct HitData {
     float4 r0, r1, r2, r3;
     float al, cr, cg, cb, Tk;
+    float t1;  // entry distance (the hit key's t)
 };
 
 // alpha of Gaussian gid along the ray, with the leaf test's own arithmetic
 __device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
                                   const int32_t *__restrict__ inv, float Q, float4 &r0, float4 &r1, float4 &r2,
-                                  float4 &r3)
+                                  float4 &r3, float &t1)
 {
     const int32_t js = inv[gid];
     r0 = records[4 * js + 0];
     r1 = records[4 * js + 1];
     r2 = records[4 * js + 2];
     r3 = records[4 * js + 3];
-    float t1, h2;
+    float h2;
     ellipsoid_hit(ray, r0, r1, r2, r3, Q, t1, h2);
     return r3.w * __expf(-0.5f * h2);
 }
@@ -392,10 +393,10 @@ __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, con
                                      const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
                                      const RenderParams &P, Accum &A, HitData &H)
 {
-    H.al = H.cr = H.cg = H.cb = 0.0f;
+    H.al = H.cr = H.cg = H.cb = H.t1 = 0.0f;
     H.Tk = A.T;
     if (act) {
-        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3);
+        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3, H.t1);
         if (!zc) {
             H.cr = rgb[3 * gid];
             H.cg = rgb[3 * gid + 1];
@@ -608,6 +609,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             // with stored hit lists the list kernel takes every ray whose list is complete
             if (S.count && S.count[ray_id] <= P.hit_cap) live = false;
         }
+        if (BWD && S.count && P.hit_cap > 0) {
+            // A ray whose list overflowed replays its hit_cap stored hits first (the list kernel's
+            // steps, same arithmetic), then traverses only for the hits after the last of them:
+            // its key (t1 recomputed bit for bit, Gaussian index) starts the rounds below. None
+            // of these rays stops within its stored hits, since it composited more.
+            for (int32_t k = 0; k < P.hit_cap; ++k) {
+                const bool act = live;
+                const uint64_t act_mask = wave_ballot(act);
+                if (act_mask == 0) break;
+                if (COUNT) c_lcomp += __popcll(act_mask);
+                const uint32_t gid = act ? uint32_t(S.ids[int64_t(k) * P.n_rays + ray_id]) : 0u;
+                HitData H;
+                composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
+                const bool stopped = act && stop_after(A, P);
+                adjoint_hit<COUNT>(act, act_mask, stopped, gid, ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
+                                   lane, c_group);
+                if (act) last = hit_key(H.t1, gid);
+                if (stopped) live = false;
+            }
+        }
         bool overflow = false;
 
         while (wave_ballot(live)) {
@@ -701,7 +722,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                             live = false;  // the second phase ends before this hit
                         } else {
                             float4 r0, r1, r2, r3;
-                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3);
+                            float t1;
+                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3, t1);
                             S.ids[int64_t(slot) * P.n_rays + ray_id] = int32_t(gid);
                             T2 *= 1.0f - al;
                             ++extra;
@@ -801,7 +823,8 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
                 if (a2) {
                     const uint32_t gid = uint32_t(S.ids[int64_t(cnt + k) * P.n_rays + LR.id]);
                     float4 r0, r1, r2, r3;
-                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3);
+                    float t1;
+                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3, t1);
                     if (!zc) {
                         const float w = T2 * al;
                         R2r = __builtin_fmaf(w, ptr.rgb[3 * gid], R2r);
