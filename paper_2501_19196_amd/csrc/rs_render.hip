@@ -797,9 +797,11 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
         float Tfin = 1.0f;
         LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
         if (LR.valid) {
+            // the paper variant packs its second-phase length above 16 bits (both are at most
+            // hit_list <= 4096 there); otherwise the count is stored as is (unbounded K_max)
             const int32_t packed = S.count[LR.id];
-            cnt = packed & 0xffff;
-            extra = packed >> 16;
+            cnt = P.paper ? packed & 0xffff : packed;
+            extra = P.paper ? packed >> 16 : 0;
             Gd.gr = S.grad[3 * LR.id];
             Gd.gg = S.grad[3 * LR.id + 1];
             Gd.gb = S.grad[3 * LR.id + 2];

@@ -284,3 +284,53 @@ def test_paper_gradient_matches_oracle(eps2):
         assert x_ref.max() == 1
     # the variant is visible in the opacity gradients (the last composited hits)
     assert np.linalg.norm(exact["opacity"] - ref["opacity"]) > 10 * REL * np.linalg.norm(ref["opacity"])
+
+
+@pytest.mark.parametrize("group,eps,tol", [("rgb", 1e-2, 1e-4), ("opacity", 1e-2, 2e-3)])
+def test_scene_scale_adjoint_directional_derivative(group, eps, tol):
+    """At the full scene-scale size (1M Gaussians, 1920x1080, stored lists of
+    capacity 512), the adjoint of F = sum_rays <g, C> along a random direction
+    v matches the central difference of the forward, which the oracle pins on
+    sampled pixels. F is linear in the colours, so the rgb case is exact up to
+    float rounding. Opacities move T, so the opacity case turns off the eps1
+    and K_max stops (a stop that moves is a jump the difference would see):
+    every ray composites all its hits, and the rays with more than 512 take
+    the overflow path (stored hits replayed, then traversal). Directions that
+    the [0, 0.999] range of the opacities would clip are left out."""
+    print("case directional", group, flush=True)
+    G, R = _g()
+    w = workload(4)
+    o, d, views = G.camera_rays(w["cams"])
+    sc = w["scene"]
+    p = R.Params(hit_list=512) if group == "rgb" else R.Params(hit_list=512, eps1=0.0, max_hits=0)
+    rng = np.random.default_rng(7)
+    g = np.float32(rng.normal(size=(o.shape[0], 3)))
+    v = np.float32(rng.normal(size=getattr(sc, group).shape))
+    if group == "opacity":
+        v[(sc.opacity - eps * np.abs(v) < 0) | (sc.opacity + eps * np.abs(v) > 0.999)] = 0.0
+    rays = G.rays_of(o, d, views)
+
+    def F(scene):
+        gs = G.gaussians(scene)
+        bvh = R.build_bvh(gs, p)
+        out, state = R.render_fwd(bvh, gs, rays, p)
+        torch.cuda.synchronize()
+        assert R.read_status(bvh) == 0
+        return float(np.sum(out.cpu().numpy().astype(np.float64) * g)), (bvh, gs, state)
+
+    f0, (bvh, gs, state) = F(sc)
+    grads = R.render_bwd(bvh, gs, rays, p, G.dev(g), state)
+    torch.cuda.synchronize()
+    got = dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in grads)))
+    analytic = float(np.sum(got[group] * v))
+
+    def shifted(sign):
+        arrs = {k: getattr(sc, k).copy() for k in GROUPS}
+        arrs[group] = np.float32(arrs[group] + sign * eps * v)
+        return type(sc)(*(arrs[k] for k in GROUPS))
+
+    fp, _ = F(shifted(+1))
+    fm, _ = F(shifted(-1))
+    numeric = (fp - fm) / (2 * eps)
+    print(group, "adjoint", analytic, "central difference", numeric, flush=True)
+    assert abs(analytic - numeric) <= tol * max(abs(numeric), 1.0)
