@@ -88,7 +88,7 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float ia = __builtin_amdgcn_rcpf(a);
     h2 = uu * ia;
     if (!(h2 <= Q)) return false;
-    const float sq = __builtin_sqrtf((Q - h2) * ia);
+    const float sq = __builtin_amdgcn_sqrtf((Q - h2) * ia);  // hardware square root (1 ulp)
     const float tc = -b * ia;
     if (b >= 0.0f) {
         t1 = tc - sq;
@@ -138,13 +138,17 @@ struct HitBuf {
         key[K - 1] = kNoHit;
     }
 
-    // sorted insert of k; the last entry falls off (inserting kNoHit changes nothing)
+    // sorted insert of k; the last entry falls off (inserting kNoHit changes nothing). The keys
+    // are never NaN, so the min/max are the bare instructions: the generic fmin/fmax would first
+    // quiet every loop-carried key (one more v_max_f64 per entry in IEEE mode).
     __device__ inline void insert(double k)
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            const double lo = __builtin_fmin(key[s], k);
-            k = __builtin_fmax(key[s], k);
+            double lo, hi;
+            asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(key[s]), "v"(k));
+            asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
+            k = hi;
             key[s] = lo;
         }
     }
