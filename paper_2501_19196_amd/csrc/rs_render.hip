@@ -484,6 +484,14 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
     }
 }
 
+// min of two floats that are never NaN-signalling, as the bare instruction
+__device__ inline float fmin_bare(float a, float b)
+{
+    float r;
+    asm("v_min_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
 constexpr int32_t kDone = INT32_MIN;
 
 // Wave-uniform descent from `node` through internal nodes to the next leaf
@@ -494,8 +502,7 @@ constexpr int32_t kDone = INT32_MIN;
 // costs one compare instead of a vote and, in simulation at the scene-scale
 // workload, visits within 0.5 % as many nodes as a majority vote.
 template <int OCT, bool COUNT>
-__device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes, const Slab &sl, uint64_t live_mask,
-                                  uint64_t lead_bit,
+__device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes, const Slab &sl, uint64_t lead_bit,
                                   float t_lo, float t_hi_w, int lane, int32_t stack_depth, int32_t &sp,
                                   int32_t &stackv, bool &overflow, uint64_t &c_node, uint64_t &c_lchild)
 {
@@ -506,11 +513,13 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
         const int2 lr = *reinterpret_cast<const int2 *>(nd + 3);
         float ln, lf, rn, rf;
         child_slabs<OCT>(n0, n1, n2, sl, ln, lf, rn, rf);
-        // [max(near, t_lo), min(widened exit, t_hi)] non-empty, as three compares (t_lo <= t_hi
-        // holds for every live lane): no min/max of the loop-invariant bounds
-        const float lx = widen_exit(lf, sl.pad), rx = widen_exit(rf, sl.pad);
-        const uint64_t bl = live_mask & wave_ballot(ln <= lx) & wave_ballot(ln <= t_hi_w) & wave_ballot(t_lo <= lx);
-        const uint64_t br = live_mask & wave_ballot(rn <= rx) & wave_ballot(rn <= t_hi_w) & wave_ballot(t_lo <= rx);
+        // [max(near, t_lo), min(widened exit, t_hi)] non-empty as two compares against
+        // x = min(widened exit, t_hi): t_lo <= t_hi holds on every live lane, and t_lo is NaN on
+        // the others, so no compare passes there. The min is the bare instruction (t_hi is
+        // loop-carried; the generic fminf would quiet it first).
+        const float lx = fmin_bare(widen_exit(lf, sl.pad), t_hi_w), rx = fmin_bare(widen_exit(rf, sl.pad), t_hi_w);
+        const uint64_t bl = wave_ballot(ln <= lx) & wave_ballot(t_lo <= lx);
+        const uint64_t br = wave_ballot(rn <= rx) & wave_ballot(t_lo <= rx);
         const int32_t left = lr.x, right = lr.y;
         if (COUNT) {
             ++c_node;
@@ -540,7 +549,7 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 
 #define RS_DESCEND_CASE(O)                                                                                    \
     case O:                                                                                                   \
-        node = descend<O, COUNT>(node, nodes, sl, live_mask, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,  \
+        node = descend<O, COUNT>(node, nodes, sl, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,             \
                                  stackv, overflow, c_node, c_lchild);                                         \
         break;
 
@@ -639,7 +648,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             HitBuf<K> hb;
             hb.clear();
             if (COUNT) ++c_round;
-            const float t_lo = last == -kNoHit ? P.t_min : fmaxf(P.t_min, hit_key_t(last));
+            // NaN on lanes that are not live: no box test passes for them
+            const float t_lo =
+                !live ? __builtin_nanf("") : (last == -kNoHit ? P.t_min : fmaxf(P.t_min, hit_key_t(last)));
             float t_hi_w = widen(tmax, sl.pad);
 
             auto leaf = [&](int64_t j) {
