@@ -87,17 +87,15 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float uu = u0 * u0 + u1 * u1 + u2 * u2;
     const float ia = __builtin_amdgcn_rcpf(a);
     h2 = uu * ia;
-    if (!(h2 <= Q)) return false;
+    // both root forms for every lane and a select, no divergent branch (t1 is only used
+    // where the ray hits, h2 <= Q, and there the chosen form is the same arithmetic)
     const float sq = __builtin_amdgcn_sqrtf((Q - h2) * ia);  // hardware square root (1 ulp)
     const float tc = -b * ia;
-    if (b >= 0.0f) {
-        t1 = tc - sq;
-    } else {
-        const float oo = o0 * o0 + o1 * o1 + o2 * o2;
-        t1 = ((oo - Q) * ia) * __builtin_amdgcn_rcpf(tc + sq);
-    }
+    const float oo = o0 * o0 + o1 * o1 + o2 * o2;
+    const float t_viete = ((oo - Q) * ia) * __builtin_amdgcn_rcpf(tc + sq);
+    t1 = b >= 0.0f ? tc - sq : t_viete;
     if (t1 == 0.0f) t1 = 0.0f;  // -0 -> +0 so the key order matches float order
-    return true;
+    return h2 <= Q;
 }
 
 // ------------------------------------------------------------- hit buffer
@@ -145,11 +143,12 @@ struct HitBuf {
     {
 #pragma unroll
         for (int s = 0; s < K; ++s) {
-            double lo, hi;
-            asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(key[s]), "v"(k));
-            asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
+            // the max first into a fresh register, then the min in place: the entry keeps its
+            // register and the carried key alternates between two, so no copies are needed
+            double hi = 0.0;
+            if (s + 1 < K) asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
+            asm volatile("v_min_f64 %0, %0, %1" : "+v"(key[s]) : "v"(k));
             k = hi;
-            key[s] = lo;
         }
     }
 };
