@@ -657,13 +657,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
                              r3 = records[4 * js + 3];
                 const uint32_t gid = uint32_t(gidx[js]);
+                // every lane evaluates the test and the key (no divergent branch); only lanes
+                // whose ray hits take part
                 float t1 = 0.0f, h2 = 0.0f;
-                bool cand = false;
-                double k = kNoHit;
-                if (live && ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2)) {
-                    k = hit_key(t1, gid);
-                    cand = t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
-                }
+                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2);
+                const double k = hit_key(t1, gid);
+                const bool cand = live && hit && t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
                 const uint64_t cmask = wave_ballot(cand);
                 if (COUNT) {
                     ++c_leaf;
