@@ -61,8 +61,14 @@ struct RenderParams {
 // Gaussians (one scale -> 0) lose no precision to cancellation. The nearer
 // root is t1 = -b/a - sqrt((Q - h^2)/a) for b = <o',d'> >= 0 and the Viete
 // form (|o'|^2 - Q) / (a t*) otherwise (Prop. 1, App. A.1).
+// Intermediates of the test that the adjoint of a hit reuses (world offset
+// x = o - m, whitened direction d', scaled cross product u, b = <o',d'>, 1/a).
+struct HitGeom {
+    float xx, xy, xz, d0, d1, d2, u0, u1, u2, b, ia;
+};
+
 __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
-                                     float Q, float &t1, float &h2)
+                                     float Q, float &t1, float &h2, HitGeom &G)
 {
     const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
     // rows of R^T
@@ -87,6 +93,7 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float uu = u0 * u0 + u1 * u1 + u2 * u2;
     const float ia = __builtin_amdgcn_rcpf(a);
     h2 = uu * ia;
+    G = HitGeom{xx, xy, xz, d0, d1, d2, u0, u1, u2, b, ia};
     // both root forms for every lane and a select, no divergent branch (t1 is only used
     // where the ray hits, h2 <= Q, and there the chosen form is the same arithmetic)
     const float sq = __builtin_amdgcn_sqrtf((Q - h2) * ia);  // hardware square root (1 ulp)
@@ -191,32 +198,16 @@ struct GradOut {
     float v[14];  // mean 3, scale 3, quat 4, opacity 1, rgb 3
 };
 
-__device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
-                                const float *__restrict__ quat, uint32_t gid, float dLda, float alpha, GradOut &G)
+__device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const HitGeom &g,
+                                float h2, const float *__restrict__ quat, uint32_t gid, float dLda, float alpha,
+                                GradOut &G)
 {
-    const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
-    const float wx = xy * ray.dz - xz * ray.dy;
-    const float wy = xz * ray.dx - xx * ray.dz;
-    const float wz = xx * ray.dy - xy * ray.dx;
+    // the test's own intermediates (same rounding as the alpha being differentiated)
+    const float xx = g.xx, xy = g.xy, xz = g.xz, d0 = g.d0, d1 = g.d1, d2 = g.d2, u0 = g.u0, u1 = g.u1, u2 = g.u2;
+    const float b = g.b, ia = g.ia;
     const float a00 = r0.x, a01 = r0.y, a02 = r0.z, a10 = r0.w, a11 = r1.x, a12 = r1.y, a20 = r1.z, a21 = r1.w,
                 a22 = r2.x;
     const float D0 = r2.y, D1 = r2.z, D2 = r2.w;
-    const float y0 = a00 * xx + a01 * xy + a02 * xz;
-    const float y1 = a10 * xx + a11 * xy + a12 * xz;
-    const float y2 = a20 * xx + a21 * xy + a22 * xz;
-    const float e0 = a00 * ray.dx + a01 * ray.dy + a02 * ray.dz;
-    const float e1 = a10 * ray.dx + a11 * ray.dy + a12 * ray.dz;
-    const float e2 = a20 * ray.dx + a21 * ray.dy + a22 * ray.dz;
-    const float v0 = a00 * wx + a01 * wy + a02 * wz;
-    const float v1 = a10 * wx + a11 * wy + a12 * wz;
-    const float v2 = a20 * wx + a21 * wy + a22 * wz;
-    const float o0 = D0 * y0, o1 = D1 * y1, o2 = D2 * y2;
-    const float d0 = D0 * e0, d1 = D1 * e1, d2 = D2 * e2;
-    const float u0 = (D1 * D2) * v0, u1 = (D0 * D2) * v1, u2 = (D0 * D1) * v2;
-    const float a = d0 * d0 + d1 * d1 + d2 * d2;
-    const float b = o0 * d0 + o1 * d1 + o2 * d2;
-    const float ia = 1.0f / a;
-    const float h2 = (u0 * u0 + u1 * u1 + u2 * u2) * ia;
     // p = (d' x u) / a
     const float p0 = (d1 * u2 - d2 * u1) * ia;
     const float p1 = (d2 * u0 - d0 * u2) * ia;
@@ -374,21 +365,21 @@ __device__ inline LaneRay lane_ray(const PT &P, const Ptrs &ptr, int64_t pkt, in
 struct HitData {
     float4 r0, r1, r2, r3;
     float al, cr, cg, cb, Tk;
-    float t1;  // entry distance (the hit key's t)
+    float t1, h2;  // entry distance (the hit key's t) and squared whitened distance
+    HitGeom g;
 };
 
 // alpha of Gaussian gid along the ray, with the leaf test's own arithmetic
 __device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
                                   const int32_t *__restrict__ inv, float Q, float4 &r0, float4 &r1, float4 &r2,
-                                  float4 &r3, float &t1)
+                                  float4 &r3, float &t1, float &h2, HitGeom &G)
 {
     const int32_t js = inv[gid];
     r0 = records[4 * js + 0];
     r1 = records[4 * js + 1];
     r2 = records[4 * js + 2];
     r3 = records[4 * js + 3];
-    float h2;
-    ellipsoid_hit(ray, r0, r1, r2, r3, Q, t1, h2);
+    ellipsoid_hit(ray, r0, r1, r2, r3, Q, t1, h2, G);
     return r3.w * __expf(-0.5f * h2);
 }
 
@@ -396,10 +387,11 @@ __device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, con
                                      const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
                                      const RenderParams &P, Accum &A, HitData &H)
 {
-    H.al = H.cr = H.cg = H.cb = H.t1 = 0.0f;
+    H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = 0.0f;
+    H.g = HitGeom{};
     H.Tk = A.T;
     if (act) {
-        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3, H.t1);
+        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3, H.t1, H.h2, H.g);
         if (!zc) {
             H.cr = rgb[3 * gid];
             H.cg = rgb[3 * gid + 1];
@@ -438,7 +430,7 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
             const float rem = Gd.gr * (Gd.Cor - A.Cr) + Gd.gg * (Gd.Cog - A.Cg) + Gd.gb * (Gd.Cob - A.Cb);
             dLda = H.Tk * (Gd.gr * H.cr + Gd.gg * H.cg + Gd.gb * H.cb) - rem / (1.0f - H.al);
         }
-        grad_hit(ray, H.r0, H.r1, H.r2, H.r3, quat, gid, dLda, H.al, G);
+        grad_hit(ray, H.r0, H.r1, H.r2, H.g, H.h2, quat, gid, dLda, H.al, G);
         const float wgt = H.al * H.Tk;
         G.v[11] = zc ? 0.0f : Gd.gr * wgt;
         G.v[12] = zc ? 0.0f : Gd.gg * wgt;
@@ -660,7 +652,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 // every lane evaluates the test and the key (no divergent branch); only lanes
                 // whose ray hits take part
                 float t1 = 0.0f, h2 = 0.0f;
-                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2);
+                HitGeom hg;
+                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2, hg);
                 const double k = hit_key(t1, gid);
                 const bool cand = live && hit && t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
                 const uint64_t cmask = wave_ballot(cand);
@@ -735,8 +728,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                             live = false;  // the second phase ends before this hit
                         } else {
                             float4 r0, r1, r2, r3;
-                            float t1;
-                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3, t1);
+                            float t1, h2;
+                            HitGeom hg;
+                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3, t1, h2, hg);
                             S.ids[int64_t(slot) * P.n_rays + ray_id] = int32_t(gid);
                             T2 *= 1.0f - al;
                             ++extra;
@@ -838,8 +832,9 @@ __global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ 
                 if (a2) {
                     const uint32_t gid = uint32_t(S.ids[int64_t(cnt + k) * P.n_rays + LR.id]);
                     float4 r0, r1, r2, r3;
-                    float t1;
-                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3, t1);
+                    float t1, h2;
+                    HitGeom hg;
+                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3, t1, h2, hg);
                     if (!zc) {
                         const float w = T2 * al;
                         R2r = __builtin_fmaf(w, ptr.rgb[3 * gid], R2r);
