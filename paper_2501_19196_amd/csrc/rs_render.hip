@@ -783,8 +783,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 // the Gaussians it composited in order; the adjoint replays that list (no
 // traversal, no hit buffer) with the forward's own per-hit arithmetic. Rays
 // whose list overflowed the capacity are left to the traversal adjoint.
+// Six waves per SIMD (80 VGPRs, a few bytes of spills) hide the gathers better than five.
 template <bool COUNT>
-__global__ __launch_bounds__(64) void k_adjoint_list(const float4 *__restrict__ records,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_adjoint_list(const float4 *__restrict__ records,
                                                      const int32_t *__restrict__ inv, const Ptrs ptr,
                                                      const RenderParams P)
 {
