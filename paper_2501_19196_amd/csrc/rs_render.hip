@@ -545,7 +545,10 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
         break;
 
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
-// (512 / waves): the adjoint carries the gradient temporaries as well.
+// (512 / waves): the adjoint carries the gradient temporaries as well. The
+// forward targets are measured optima: a few dozen bytes of scratch spills
+// (kbuf 24 at five waves, 48 at three) cost less than the node-fetch latency
+// the extra wave hides, while larger spills (kbuf 24 at six, 32 at five) lose.
 #ifndef RS_FWD16_WAVES
 #define RS_FWD16_WAVES 5
 #endif
@@ -553,15 +556,21 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 #define RS_BWD16_WAVES 4
 #endif
 #ifndef RS_FWD24_WAVES
-#define RS_FWD24_WAVES 4
+#define RS_FWD24_WAVES 5
 #endif
 #ifndef RS_BWD24_WAVES
 #define RS_BWD24_WAVES 3
 #endif
+#ifndef RS_FWD32_WAVES
+#define RS_FWD32_WAVES 4
+#endif
+#ifndef RS_FWD48_WAVES
+#define RS_FWD48_WAVES 3
+#endif
 constexpr int waves_for(int K, bool bwd)
 {
     return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : (K <= 32 ? 2 : 1))))
-               : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : (K <= 32 ? 3 : 2))));
+               : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : (K <= 32 ? RS_FWD32_WAVES : RS_FWD48_WAVES))));
 }
 
 template <int K, bool BWD, bool BRUTE, bool COUNT>
