@@ -1032,7 +1032,7 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
             int dev = 0, cus = 256;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-            const int64_t waves = int64_t(cus) * 16;  // 4 waves per SIMD
+            const int64_t waves = int64_t(cus) * 24;  // up to 6 waves per SIMD (the most any variant fits)
             grid = int(waves < P.n_packets ? waves : P.n_packets);
         } else {
             const int64_t deal = int64_t(kXcdQueues) * kXcdRun;
