@@ -549,6 +549,9 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 // forward targets are measured optima: a few dozen bytes of scratch spills
 // (kbuf 24 at five waves, 48 at three) cost less than the node-fetch latency
 // the extra wave hides, while larger spills (kbuf 24 at six, 32 at five) lose.
+// The adjoint's are measured the same way: kbuf 24 and 32 at four waves and
+// 48 at three beat one wave fewer by 10-20 %, while one wave more (five, and
+// four for 48) spills heavily and doubles the time.
 #ifndef RS_FWD16_WAVES
 #define RS_FWD16_WAVES 5
 #endif
@@ -559,7 +562,13 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 #define RS_FWD24_WAVES 5
 #endif
 #ifndef RS_BWD24_WAVES
-#define RS_BWD24_WAVES 3
+#define RS_BWD24_WAVES 4
+#endif
+#ifndef RS_BWD32_WAVES
+#define RS_BWD32_WAVES 4
+#endif
+#ifndef RS_BWD48_WAVES
+#define RS_BWD48_WAVES 3
 #endif
 #ifndef RS_FWD32_WAVES
 #define RS_FWD32_WAVES 4
@@ -569,7 +578,7 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 #endif
 constexpr int waves_for(int K, bool bwd)
 {
-    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : (K <= 32 ? 2 : 1))))
+    return bwd ? (K <= 8 ? 4 : (K <= 16 ? RS_BWD16_WAVES : (K <= 24 ? RS_BWD24_WAVES : (K <= 32 ? RS_BWD32_WAVES : RS_BWD48_WAVES))))
                : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : (K <= 32 ? RS_FWD32_WAVES : RS_FWD48_WAVES))));
 }
 
