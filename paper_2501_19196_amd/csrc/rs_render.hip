@@ -801,9 +801,13 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 // the Gaussians it composited in order; the adjoint replays that list (no
 // traversal, no hit buffer) with the forward's own per-hit arithmetic. Rays
 // whose list overflowed the capacity are left to the traversal adjoint.
-// Six waves per SIMD (80 VGPRs, a few bytes of spills) hide the gathers better than five.
+// Six waves per SIMD (80 VGPRs, a few bytes of spills) hide the gathers better
+// than five; seven and eight spill 56 and 88 bytes per lane and lose 5 and 30 %.
+#ifndef RS_LIST_WAVES
+#define RS_LIST_WAVES 6
+#endif
 template <bool COUNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) void k_adjoint_list(const float4 *__restrict__ records,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVES))) void k_adjoint_list(const float4 *__restrict__ records,
                                                      const int32_t *__restrict__ inv, const Ptrs ptr,
                                                      const RenderParams P)
 {
