@@ -109,7 +109,8 @@ typedef struct {
 
 /* Renderer knobs. Q: ellipsoid quantile (Sec. 3; > 0). eps1: transmittance
  * threshold (>= 0). t_min: minimum hit depth (finite, >= 0). max_hits: K_max (0 = unbounded).
- * kbuf: hits gathered per ray per traversal round (8, 16, 24, 32 or 48; 0 = 24; the
+ * kbuf: hits gathered per ray per traversal round (8, 16, 24, 32 or 48; 0 = 48,
+ * the size rs_autotune picks for the forward on every measured workload; the
  * result does not depend on it).
  * stack_depth: traversal stack entries (1..64; 0 = 64). tile_width: width in
  * pixels of the 64-ray packet tile of a view (4, 8, 16 or 32, i.e. 4x16, 8x8,

@@ -1063,7 +1063,7 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
             else
                 k_adjoint_list<false><<<grid, kWave, 0, st>>>(records, inv, ptr, P);
         } else {
-            const int K = p->kbuf > 0 ? p->kbuf : 24;
+            const int K = p->kbuf > 0 ? p->kbuf : 48;
             switch (K) {
             case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
             case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
