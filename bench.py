@@ -96,9 +96,8 @@ def main():
     g = R.Gaussians(*(t(a) for a in sc.arrays()))
     rays = R.Rays(t(o), t(d), views=views)
     fixed = args.kbuf or args.persistent or args.tile_width
-    # the mesh render keeps lists for its three ray sets in the frame: capacity capped at 256
     base = R.Params(kbuf=args.kbuf, flags=(2 if args.persistent else 0) | (16 if args.paper_gradient else 0),
-                    tile_width=args.tile_width, hit_list=args.hit_list if mesh_np is None else min(args.hit_list, 256),
+                    tile_width=args.tile_width, hit_list=args.hit_list,
                     eps2=args.eps2)
     nr = o.shape[0]
     n = sc.n
@@ -157,7 +156,7 @@ def main():
                                         flags=(base.flags & ~2) | (2 if shape[1] else 0))
                 render(bvh, g, p, out)
                 ms = []
-                for _ in range(2):
+                for _ in range(3):
                     e0, e1 = ev(), ev()
                     e0.record()
                     render(bvh, g, p, out)
