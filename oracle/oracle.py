@@ -50,8 +50,11 @@ class _Rays(C.Structure):
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        L = C.CDLL(_LIB_PATH)
+        # RS_ORACLE_LIB names another build of the same sources (the sanitizer test's)
+        path = os.environ.get("RS_ORACLE_LIB")
+        if not path:
+            build(force=False)
+        L = C.CDLL(path or _LIB_PATH)
         P = C.c_void_p
         L.orc_version.restype = C.c_int
         L.orc_max_threads.restype = C.c_int
@@ -62,6 +65,7 @@ def lib():
         L.orc_ray_hits.argtypes = [P, P, C.c_int64, P, C.c_int64, P, P, P, P]
         L.orc_ray_hits.restype = C.c_int64
         L.orc_render_fwd.argtypes = [P, P, P, P, P, P, C.c_int]
+        L.orc_render_lists.argtypes = [P, P, P, C.c_int64, P, P, C.c_int]
         L.orc_render_bwd.argtypes = [P, P, P, P, P, P, P, P, P, P, C.c_int]
         L.orc_render_bwd_paper.argtypes = [P, P, P, C.c_double, P, P, P, P, P, P, P, P, C.c_int]
         L.orc_ray_dC_dalpha.argtypes = [P, P, C.c_int64, P, C.c_int64, P]
@@ -135,6 +139,20 @@ def render_fwd(scene, origin, direction, params=None, t_max=None, bg=None, threa
     p = params.c()
     lib().orc_render_fwd(C.byref(b.sc), C.byref(b.rays), C.byref(p), _ptr(out), _ptr(T), _ptr(L), int(threads))
     return out, T, L
+
+
+def render_lists(scene, origin, direction, params=None, cap=512, t_max=None, bg=None, threads=0):
+    """The composited hits of every ray in compositing order: (ids[n, cap] int64
+    with -1 after the first min(L, cap), L[n] int64)."""
+    params = params or Params()
+    b = _Bound(scene, origin, direction, t_max, bg)
+    n = b.o.shape[0]
+    ids = np.zeros((n, max(int(cap), 1)), np.int64)
+    L = np.zeros(n, np.int64)
+    p = params.c()
+    lib().orc_render_lists(C.byref(b.sc), C.byref(b.rays), C.byref(p), int(max(cap, 1)), _ptr(ids), _ptr(L),
+                           int(threads))
+    return ids, L
 
 
 def render_bwd(scene, origin, direction, grad_rgb, params=None, t_max=None, bg=None, threads=0, want_bg=False):

@@ -367,6 +367,27 @@ int orc_render_fwd(const orc_scene *sc, const orc_rays *r, const orc_params *p,
     return 0;
 }
 
+/* The composited hits of every ray in compositing order (Eq. 3 with the K_max
+ * and eps1 rules): ids[k][0..cap) holds the first min(L, cap) Gaussian indices,
+ * then -1; L_out[k] = L. */
+int orc_render_lists(const orc_scene *sc, const orc_rays *r, const orc_params *p, int64_t cap, int64_t *ids,
+                     int64_t *L_out, int nthreads)
+{
+    set_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t k = 0; k < r->n; ++k) {
+        double o[3], d[3], T, C[3];
+        ray_of(r, k, o, d);
+        orc_hit *h;
+        int64_t n = collect(sc, o, d, p, tmax_of(r, k), &h);
+        int64_t L = composite(sc, p, h, n, bg_of(r, p, k), C, &T);
+        for (int64_t j = 0; j < cap; ++j) ids[k * cap + j] = j < L ? h[j].idx : -1;
+        L_out[k] = L;
+        free(h);
+    }
+    return 0;
+}
+
 /* dC/dalpha_k and dC/dc_k weights for one composited list (division-free,
  * back to front). grad: upstream dL/dC (3). Writes g_alpha[k] = <grad, dC/dalpha_k>
  * and w[k] = alpha_k T_k (so dL/dc_k = grad * w[k]). Returns L. */

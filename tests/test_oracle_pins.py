@@ -419,3 +419,37 @@ def test_rgb_gradient_closed_form(orc):
     want[idx] = al * T
     np.testing.assert_allclose(grads["rgb"][:, 0], want, atol=1e-15)
     assert np.all(grads["rgb"][:, 1:] == 0)
+
+
+@pytest.mark.parametrize("max_hits,eps1", [(0, 0.0), (6, 1e-4), (512, 0.2)])
+def test_render_lists_are_the_sorted_composited_hits(orc, max_hits, eps1):
+    """orc_render_lists against an independent assembly: the per-Gaussian test
+    of every Gaussian, a Python sort by (t1, index), and Eq. 3 with the K_max
+    and eps1 rules written out here; its L is render_fwd's, and compositing its
+    ids reproduces render_fwd's colour."""
+    sc = scenes.random_scene(33, 150)
+    o, d = _rays(40, 34)
+    p = orc.Params(max_hits=max_hits, eps1=eps1, bg=(0.3, 0.2, 0.1))
+    ids, L = orc.render_lists(sc, o, d, p, cap=64)
+    rgb, _, L_fwd = orc.render_fwd(sc, o, d, p)
+    np.testing.assert_array_equal(L, L_fwd)
+    for k in range(len(o)):
+        hits = []
+        for i in range(sc.n):
+            h, t, h2 = orc.intersect(sc, i, o[k], d[k])
+            if h:
+                hits.append((t, i, float(sc.opacity[i]) * np.exp(-0.5 * h2)))
+        hits.sort()
+        T, C, n = 1.0, np.zeros(3), 0
+        for t, i, a in hits:
+            if max_hits and n >= max_hits:
+                break
+            C += T * a * sc.rgb[i].astype(np.float64)
+            T *= 1.0 - a
+            n += 1
+            if T < eps1:
+                break
+        assert L[k] == n
+        np.testing.assert_array_equal(ids[k, :min(n, 64)], [i for _, i, _ in hits[:min(n, 64)]])
+        assert np.all(ids[k, min(n, 64):] == -1)
+        np.testing.assert_allclose(C + T * np.asarray(p.bg), rgb[k], rtol=1e-12, atol=1e-14)
