@@ -226,7 +226,7 @@ def ray_alternatives(scene, origin, direction, k, params=None, dh=1e-5, dt=1e-6,
     return out[:min(n, cap)]
 
 
-def alternatives_batch(scene, origin, direction, params=None, dh=1e-4, dt=1e-5, dT=1e-3, max_events=3,
+def alternatives_batch(scene, origin, direction, params=None, dh=1e-4, dt=5e-6, dT=1e-3, max_events=3,
                        t_max=None, bg=None, cap=16, threads=0):
     """Per ray: (count[n], colours[n, cap, 3]); count -1 marks an unresolved ray."""
     params = params or Params()
@@ -245,6 +245,10 @@ def compare_with_alternatives(gpu_rgb, ref_rgb, scene, origin, direction, params
     """Parity protocol: a ray passes when |gpu - oracle| <= tol per channel, or
     when its colour is within tol of one of the oracle's rounding-level
     alternatives. Returns a dict of counts and the worst error after the protocol."""
+    # up to 8 events (256 alternatives) per pixel: dense scenes put several near-tied
+    # pairs on one ray
+    win.setdefault("max_events", 8)
+    win.setdefault("cap", 256)
     gpu = np.asarray(gpu_rgb, np.float64).reshape(-1, 3)
     ref = np.asarray(ref_rgb, np.float64).reshape(-1, 3)
     err = np.abs(gpu - ref).max(axis=1)
