@@ -5,9 +5,19 @@ A step is one pass of the whole hot path over one workload: BVH rebuild
 an L1 loss against a fixed target image, and the adjoint render producing
 gradients for all five parameter groups. Inputs are resident in HBM before the
 timed region. The default workload is the scene-scale one (1M Gaussians, one
-1920x1080 view); --workload 3 (8 views) also times one launch per view against
-the batched launch, --workload 5 runs the mesh path (reflection and shadow
-rays), --workload 6 the three-bounce path with glass and a mirror.
+1920x1080 view); --workload 3 (8 views), 5 (the mesh path: reflection and
+shadow rays) and 6 (three bounces with glass and a mirror) select the others.
+
+The line also carries:
+  - the same step with the adjoint that re-traverses the BVH back to front
+    instead of replaying stored hit lists ("recompute");
+  - the batched persistent launch against one launch per view, forward and
+    forward+backward, on the 8-view batch (300k Gaussians) and on the mesh
+    workload's primary rays (500k Gaussians, 4 views of 1024x768), each form
+    captured in a HIP graph ("batching"; --no-batching skips it);
+  - the roofline of the dominant kernel against HBM (compulsory bytes over the
+    kernel time; counter bytes when the committed rocprofv3 record matches the
+    sources; a device copy measured here) and against the FP32 vector peak.
 
 The launch shape (hit-buffer size, grid form, packet tile) is autotuned on the
 workload before timing unless --no-autotune; the timed steps replay a HIP
@@ -19,6 +29,7 @@ Prints one JSON line. `value` is forward+backward throughput in Mrays/s
 
 import argparse
 import dataclasses
+import hashlib
 import json
 import os
 import sys
@@ -28,6 +39,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Mrays/s fwd and fwd+bwd at 1M Gaussians, % HBM roofline, vs oracle error"
+PEAK_HBM_GBS = 8000.0     # MI355X HBM3E, AMD public figure
+PEAK_FP32_TFLOPS = 157.3  # MI355X FP32 vector, AMD public figure
 
 # Algorithmic FP32 work of the render kernels per unit of the library's work
 # counters (an FMA is 2, min/max/compare/rcp/sqrt/exp are 1):
@@ -35,6 +48,15 @@ FLOPS_CHILD = 22.0      # child-box slab test whose box the lane's ray overlaps
 FLOPS_LEAF = 90.0       # ray / ellipsoid test of a live lane at a visited leaf
 FLOPS_COMPOSITE = 110.0  # composited hit (alpha recomputed + Eq. 3 step)
 FLOPS_ADJOINT = 265.0    # adjoint of a composited hit (dL/dalpha + App. A.6)
+
+# Compulsory HBM bytes (each item moved once, perfect reuse) per unit:
+RAY_FWD_BYTES = 24 + 12 + 32   # ray origin + direction in, colour out, ray state out (final colour/T, start key)
+RAY_LIST_BYTES = 16            # list bookkeeping out (stored hit lists)
+SLOT_BYTES = 4                 # one stored Gaussian id per composited hit (written, then read by the adjoint)
+GAUSS_FWD_BYTES = 64 + 12 + 4 + 4   # record (R^T, 1/s, mean, opacity), colour, sorted -> index, index -> sorted
+NODE_BYTES = 64                # BVH node (two child boxes, two child refs)
+RAY_BWD_BYTES = 12 + 32        # upstream gradient, ray state in
+GAUSS_BWD_BYTES = 64 + 12 + 16 + 4 + 128  # record, colour, quaternion, index -> sorted, accumulator line r+w
 
 
 def parse():
@@ -47,17 +69,19 @@ def parse():
     ap.add_argument("--persistent", action="store_true", help="persistent grid (implies --no-autotune)")
     ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
     ap.add_argument("--hit-list", type=int, default=512,
-                    help="stored hit-list capacity per ray (0 = the adjoint re-traverses the BVH)")
+                    help="stored hit-list pool, slots per ray (0 = the adjoint re-traverses the BVH)")
     ap.add_argument("--paper-gradient", action="store_true",
-                    help="the paper's backward variant (second threshold eps2 = --eps2); needs --hit-list >= 512")
+                    help="the paper's backward variant (second threshold eps2 = --eps2)")
     ap.add_argument("--eps2", type=float, default=1e-4)
     ap.add_argument("--loss", choices=("l1", "paper"), default="l1",
                     help="l1: mean L1 (gradient by torch); paper: (1 - 0.2) L2 + 0.2 D-SSIM per view (rs_loss)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-recompute", action="store_true", help="skip the re-traversing adjoint's step")
+    ap.add_argument("--no-batching", action="store_true", help="skip the batched vs per-view comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=8000)
-    ap.add_argument("--parity-rays", type=int, default=256)
+    ap.add_argument("--parity-rays", type=int, default=2048)
     ap.add_argument("--profile", action="store_true",
                     help="one warm-up and one step, then a 256 MiB device copy that calibrates the "
                          "FETCH_SIZE / WRITE_SIZE counters; prints no JSON line")
@@ -66,6 +90,17 @@ def parse():
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def compulsory_fwd(rays, n, composited, lists):
+    return rays * (RAY_FWD_BYTES + (RAY_LIST_BYTES if lists else 0)) + (composited * SLOT_BYTES if lists else 0) \
+        + n * GAUSS_FWD_BYTES + max(n - 1, 0) * NODE_BYTES
+
+
+def compulsory_bwd(rays, n, composited, lists):
+    traversal = 0 if lists else max(n - 1, 0) * NODE_BYTES + n * 4  # nodes and sorted -> index, re-traversed
+    return rays * (RAY_BWD_BYTES + (RAY_LIST_BYTES if lists else 0)) + (composited * SLOT_BYTES if lists else 0) \
+        + n * GAUSS_BWD_BYTES + traversal
 
 
 def main():
@@ -109,17 +144,24 @@ def main():
         mbvh = R.build_mesh_bvh(dm)
         L = w["light"]
         shading = R.Shading(light=(float(L[0]), float(L[1]), float(L[2])), max_bounces=int(w.get("bounces", 1)))
-    frame = R.mesh_frame(nr, base, shading=shading) if mesh_np is not None else None
+
+    frames = {}
+
+    def frame_for(p):
+        key = p.hit_list
+        if key not in frames:
+            frames[key] = R.mesh_frame(nr, p, shading=shading)
+        return frames[key]
 
     def render(bvh, gs, p, out, state=None):
         if mesh_np is not None:
-            R.render_mesh_fwd(bvh, mbvh, gs, dm, shading, rays, p, out=out, frame=frame)
+            R.render_mesh_fwd(bvh, mbvh, gs, dm, shading, rays, p, out=out, frame=frame_for(p))
         else:
-            R.render_fwd(bvh, gs, rays, p, out=out, state=state)
+            R.render_fwd(bvh, gs, rays, p, out=out, state=state, want_state=state is not None)
 
     def adjoint(bvh, p, grad, state):
         if mesh_np is not None:
-            R.render_mesh_bwd(bvh, mbvh, g, dm, shading, rays, p, grad, frame, grads=grads)
+            R.render_mesh_bwd(bvh, mbvh, g, dm, shading, rays, p, grad, frame_for(p), grads=grads)
         else:
             R.render_bwd(bvh, g, rays, p, grad, state, grads=grads)
 
@@ -132,46 +174,57 @@ def main():
 
     ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device=dev)
     out = torch.empty((nr, 3), dtype=torch.float32, device=dev)
-    state = R.new_state(nr, base, dev)  # colour + T, and the stored hit lists
+    states = {}
+
+    def state_for(p):
+        if p.hit_list not in states:
+            states[p.hit_list] = R.new_state(nr, p, dev)
+        return states[p.hit_list]
+
     grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
              torch.empty_like(g.opacity), torch.empty_like(g.rgb))
     ev = lambda: torch.cuda.Event(enable_timing=True)
 
-    # ---- launch shape: autotuned on this workload (plain render form)
-    pf = pb = base
-    tune = None
-    if not fixed and not args.no_autotune and not args.profile:
-        bvh = R.build_bvh(g, base, workspace=ws)
-        R.render_fwd(bvh, g, rays, base, out=out, state=state)
+    def tune_for(p):
+        """Autotuned (forward, adjoint) params for the stored-list setting of p."""
+        bvh = R.build_bvh(g, p, workspace=ws)
+        st = state_for(p)
+        R.render_fwd(bvh, g, rays, p, out=out, state=st)
         gr = torch.sign(out - target) * (1.0 / (3.0 * nr))
         t1 = time.time()
-        pf, pb, rows = R.autotune(bvh, g, rays, base, grad_rgb=gr, reps=2)
+        pf, pb, rows = R.autotune(bvh, g, rays, p, grad_rgb=gr, reps=2)
         if mesh_np is not None:
             # the mesh forward traces the secondary ray sets in the same launch, and
             # those favour other shapes than the primaries the library timed: time
             # every shape on the launch the step makes
             best = None
             for shape in dict.fromkeys((r["kbuf"], r["persistent"], r["tile_width"]) for r in rows):
-                p = dataclasses.replace(base, kbuf=shape[0], tile_width=shape[2],
-                                        flags=(base.flags & ~2) | (2 if shape[1] else 0))
-                render(bvh, g, p, out)
+                q = dataclasses.replace(p, kbuf=shape[0], tile_width=shape[2],
+                                        flags=(p.flags & ~2) | (2 if shape[1] else 0))
+                render(bvh, g, q, out)
                 ms = []
                 for _ in range(3):
                     e0, e1 = ev(), ev()
                     e0.record()
-                    render(bvh, g, p, out)
+                    render(bvh, g, q, out)
                     e1.record()
                     e1.synchronize()
                     ms.append(e0.elapsed_time(e1))
                 if best is None or min(ms) < best[0]:
-                    best = (min(ms), p)
+                    best = (min(ms), q)
             pf = best[1]
-        tune = dict(fwd=dict(kbuf=pf.kbuf, persistent=bool(pf.flags & 2), tile_width=pf.tile_width),
+        info = dict(fwd=dict(kbuf=pf.kbuf, persistent=bool(pf.flags & 2), tile_width=pf.tile_width),
                     bwd=dict(kbuf=pb.kbuf, persistent=bool(pb.flags & 2), tile_width=pb.tile_width),
                     candidates=len(rows), seconds=round(time.time() - t1, 2))
+        return pf, pb, info
+
+    # ---- launch shape: autotuned on this workload
+    pf = pb = base
+    tune = None
+    if not fixed and not args.no_autotune and not args.profile:
+        pf, pb, tune = tune_for(base)
         log("autotune", tune)
 
-    kt = {"build": [], "fwd": [], "bwd": []}
     lws = [R.loss_workspace(vw, vh, dev) for _, vw, vh in views] if args.loss == "paper" else None
     lval = torch.empty(max(len(views), 1), dtype=torch.float32, device=dev)
     lgrad = torch.empty((nr, 3), dtype=torch.float32, device=dev)
@@ -184,27 +237,39 @@ def main():
             R.image_loss(out[sl], target[sl], vw, vh, 0.2, ws=lws[k], out=lval[k:k + 1], grad_out=lgrad[sl])
         return lgrad
 
-    def step(record=False):
-        e = [ev() for _ in range(5)] if record else None
-        if record:
-            e[0].record()
-        bvh = R.build_bvh(g, base, workspace=ws)
-        if record:
-            e[1].record()
-        render(bvh, g, pf, out, state)
-        if record:
-            e[2].record()
-        grad = loss_grad()
-        if record:
-            e[3].record()
-        adjoint(bvh, pb, grad, state)
-        if record:
-            e[4].record()
-        return e
+    held = {}
 
-    def fwd_step():
-        bvh = R.build_bvh(g, base, workspace=ws)
-        render(bvh, g, pf, out, None)
+    def make_step(qf, qb):
+        st = state_for(qf)
+
+        def step(record=False):
+            e = [ev() for _ in range(5)] if record else None
+            if record:
+                e[0].record()
+            bvh = R.build_bvh(g, base, workspace=ws)
+            if record:
+                e[1].record()
+            render(bvh, g, qf, out, st)
+            if record:
+                e[2].record()
+            grad = loss_grad()
+            if record:
+                e[3].record()
+            adjoint(bvh, qb, grad, st)
+            if record:
+                e[4].record()
+            held["bvh"] = bvh
+            return e
+        return step
+
+    def make_fwd_step(qf):
+        def fwd_step():
+            bvh = R.build_bvh(g, base, workspace=ws)
+            render(bvh, g, qf, out, None)
+        return fwd_step
+
+    step = make_step(pf, pb)
+    fwd_step = make_fwd_step(pf)
 
     if args.profile:
         step()
@@ -218,11 +283,6 @@ def main():
         log("profile step done")
         return
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    status = R.read_status(R.build_bvh(g, base, workspace=ws))
-
     def timed(fn, steps):
         s0, s1 = ev(), ev()
         torch.cuda.synchronize()
@@ -232,111 +292,158 @@ def main():
         torch.cuda.synchronize()
         return s0.elapsed_time(s1) / steps, res
 
-    # eager steps, with per-phase events
-    ms_eager, recs = timed(lambda: step(True), args.steps)
-    for e in recs:
-        kt["build"].append(e[0].elapsed_time(e[1]))
-        kt["fwd"].append(e[1].elapsed_time(e[2]))
-        kt["bwd"].append(e[3].elapsed_time(e[4]))
-    ms_fwd_eager, _ = timed(fwd_step, args.steps)
-
-    # HIP-graph replays of the same steps
-    ms_graph = ms_fwd_graph = None
-    if not args.no_graph:
-        graphs = []
-        for fn in (step, fwd_step):
-            side = torch.cuda.Stream()
-            side.wait_stream(torch.cuda.current_stream())
-            with torch.cuda.stream(side):
-                fn()
-            torch.cuda.current_stream().wait_stream(side)
-            torch.cuda.synchronize()
-            gph = torch.cuda.CUDAGraph()
-            with torch.cuda.graph(gph):
-                fn()
-            torch.cuda.synchronize()
-            gph.replay()
-            torch.cuda.synchronize()
-            graphs.append(gph)
-        ms_graph, _ = timed(graphs[0].replay, args.steps)
-        ms_fwd_graph, _ = timed(graphs[1].replay, args.steps)
-        step()  # leave eager results (out, grads) of the current parameters
+    def graph_of(fn):
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            fn()
+        torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
-    ms_step = ms_graph if ms_graph is not None else ms_eager
-    ms_fwd = ms_fwd_graph if ms_fwd_graph is not None else ms_fwd_eager
+        gph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(gph):
+            fn()
+        torch.cuda.synchronize()
+        gph.replay()
+        torch.cuda.synchronize()
+        return gph
 
-    med = {k: float(np.median(v)) for k, v in kt.items()}
+    def measure(step_fn, fwd_fn):
+        """Eager steps with per-phase events, then HIP-graph replays of the step and of
+        the forward step; returns (ms_step, ms_fwd, ms_eager, ms_fwd_eager, phase medians)."""
+        for _ in range(args.warmup):
+            step_fn()
+        torch.cuda.synchronize()
+        kt = {"build": [], "fwd": [], "bwd": []}
+        ms_eager, recs = timed(lambda: step_fn(True), args.steps)
+        for e in recs:
+            kt["build"].append(e[0].elapsed_time(e[1]))
+            kt["fwd"].append(e[1].elapsed_time(e[2]))
+            kt["bwd"].append(e[3].elapsed_time(e[4]))
+        ms_fwd_eager, _ = timed(fwd_fn, args.steps)
+        ms_graph = ms_fwd_graph = None
+        if not args.no_graph:
+            ga, gb = graph_of(step_fn), graph_of(fwd_fn)
+            ms_graph, _ = timed(ga.replay, args.steps)
+            ms_fwd_graph, _ = timed(gb.replay, args.steps)
+            del ga, gb
+        med = {k: float(np.median(v)) for k, v in kt.items()}
+        return (ms_graph if ms_graph is not None else ms_eager,
+                ms_fwd_graph if ms_fwd_graph is not None else ms_fwd_eager, ms_eager, ms_fwd_eager, med)
+
+    ms_step, ms_fwd, ms_eager, ms_fwd_eager, med = measure(step, fwd_step)
+    status = R.read_status(held["bvh"])  # the last timed step's own workspace, not rebuilt
     mrays_fb = nr / (ms_step * 1e-3) / 1e6
     mrays_f = nr / (ms_fwd * 1e-3) / 1e6
     mrays_render = nr / (med["fwd"] * 1e-3) / 1e6
+    log(f"step {ms_step:.3f} ms ({mrays_fb:.1f} Mrays/s), phases {med}, status {status}")
 
-    # ---- batched multi-view launch vs one launch per view (forward and adjoint render only)
-    batching = None
-    if len(views) > 1 and mesh_np is None:
-        bvh = R.build_bvh(g, base, workspace=ws)
-        gr = torch.sign(out - target) * (1.0 / (3.0 * nr))
-        # per-view slices of the ray state need the plain layout: this comparison recomputes
-        pf, pb = dataclasses.replace(pf, hit_list=0), dataclasses.replace(pb, hit_list=0)
-        state = torch.empty((nr, 4), dtype=torch.float32, device=dev)
-        per_rays = [R.Rays(rays.origin[off:off + vw * vh], rays.direction[off:off + vw * vh],
-                           views=[(0, vw, vh)]) for off, vw, vh in views]
-
-        def per_view_fwd():
-            for (off, vw, vh), rr in zip(views, per_rays):
-                R.render_fwd(bvh, g, rr, pf, out=out[off:off + vw * vh], state=state[off:off + vw * vh])
-
-        def per_view_bwd():
-            for (off, vw, vh), rr in zip(views, per_rays):
-                R.render_bwd(bvh, g, rr, pb, gr[off:off + vw * vh], state[off:off + vw * vh], grads=grads)
-
-        per_view_fwd()
-        ms_pv_f, _ = timed(per_view_fwd, args.steps)
-        ms_pv_b, _ = timed(per_view_bwd, args.steps)
-        ms_b_f, _ = timed(lambda: R.render_fwd(bvh, g, rays, pf, out=out, state=state), args.steps)
-        ms_b_b, _ = timed(lambda: R.render_bwd(bvh, g, rays, pb, gr, state, grads=grads), args.steps)
-        batching = dict(batched_fwd_ms=round(ms_b_f, 4), per_view_fwd_ms=round(ms_pv_f, 4),
-                        batched_bwd_ms=round(ms_b_b, 4), per_view_bwd_ms=round(ms_pv_b, 4),
-                        note="per-view: one render launch per view (bwd: per view, accumulating gradients "
-                             "only within its own launch)")
-        pf, pb = dataclasses.replace(pf, hit_list=base.hit_list), dataclasses.replace(pb, hit_list=base.hit_list)
-        state = R.new_state(nr, base, dev)
-        step()
+    # ---- the same step with the adjoint that re-traverses the BVH (no stored lists)
+    recompute = None
+    if not args.no_recompute and base.hit_list > 0 and not args.paper_gradient:
+        b0 = dataclasses.replace(base, hit_list=0)
+        rf, rb = dataclasses.replace(pf, hit_list=0), dataclasses.replace(pb, hit_list=0)
+        rtune = None
+        if not fixed and not args.no_autotune:
+            rf, rb, rtune = tune_for(b0)
+        r_step, r_fwd, r_eager, _, r_med = measure(make_step(rf, rb), make_fwd_step(rf))
+        recompute = dict(value=round(nr / (r_step * 1e-3) / 1e6, 3), ms_per_step=round(r_step, 4),
+                         eager_ms_per_step=round(r_eager, 4),
+                         kernel_ms_median={k: round(v, 4) for k, v in r_med.items()},
+                         launch_bwd=dict(kbuf=rb.kbuf or 48, persistent=bool(rb.flags & 2),
+                                         tile_width=rb.tile_width or 8), autotune=rtune,
+                         status=R.read_status(held["bvh"]))
+        log("recompute", recompute)
+        states.pop(0, None)
+        step()  # leave the stored-list step's results
         torch.cuda.synchronize()
 
-    # ---- algorithmic FLOPs from the library's work counters (one untimed forward + adjoint)
-    qf = R.Params(**{**pf.__dict__, "flags": pf.flags | 8})
-    qb = R.Params(**{**pb.__dict__, "flags": pb.flags | 8})
+    # ---- algorithmic work from the library's counters (one untimed forward + adjoint)
+    qf = dataclasses.replace(pf, flags=pf.flags | 8)
+    qb = dataclasses.replace(pb, flags=pb.flags | 8)
+    st = state_for(pf)
     bvh_c = R.build_bvh(g, qf, workspace=ws)
-    render(bvh_c, g, qf, out, state)
+    render(bvh_c, g, qf, out, st)
     cf = R.read_counters(bvh_c)
-    adjoint(bvh_c, qb, torch.sign(out - target) * (1.0 / (3.0 * nr)), state)
-    cb = {k: R.read_counters(bvh_c)[k] - cf[k] for k in cf}
+    adjoint(bvh_c, qb, torch.sign(out - target) * (1.0 / (3.0 * nr)), st)
+    c2 = R.read_counters(bvh_c)
+    cb = {k: c2[k] - cf[k] for k in cf}
+    lists = base.hit_list > 0
+    comp = cf["lane_composited"]
     fwd_flops = FLOPS_CHILD * cf["lane_child_overlaps"] + FLOPS_LEAF * cf["lane_leaf_tests"] + \
-        FLOPS_COMPOSITE * cf["lane_composited"]
-    # the adjoint replays composited hits from the stored lists (r10) or by re-traversal
+        FLOPS_COMPOSITE * comp
+    # the adjoint replays composited hits from the stored lists or by re-traversal
     bwd_flops = FLOPS_CHILD * cb["lane_child_overlaps"] + FLOPS_LEAF * cb["lane_leaf_tests"] + \
-        (FLOPS_COMPOSITE + FLOPS_ADJOINT) * (cb["lane_composited"] + cb["r10"])
+        (FLOPS_COMPOSITE + FLOPS_ADJOINT) * (cb["lane_composited"] + cb["list_composited"])
     dom = "bwd" if med["bwd"] >= med["fwd"] else "fwd"
+    dom_ms = med[dom]
+    n_rays_all = nr  # primaries (the mesh workloads trace up to 2B more rays per pixel in the same launch)
+    comp_bytes = compulsory_fwd(n_rays_all, n, comp, lists) if dom == "fwd" else \
+        compulsory_bwd(n_rays_all, n, cb["list_composited"] + cb["lane_composited"], lists)
+    achieved_hbm = comp_bytes / (dom_ms * 1e-3) / 1e9
     dom_flops = bwd_flops if dom == "bwd" else fwd_flops
-    achieved = dom_flops / (med[dom] * 1e-3) / 1e12
+    achieved_alu = dom_flops / (dom_ms * 1e-3) / 1e12
 
     # HBM traffic per launch from committed rocprofv3 FETCH_SIZE / WRITE_SIZE passes, used
     # only when they were taken on the current render and BVH sources, this workload and,
     # for the forward, this launch shape
     traffic = None
     try:
-        import hashlib
         rec = json.load(open(os.path.join(ROOT, "profiles", "render_traffic.json")))
         src = b"".join(open(os.path.join(ROOT, "paper_2501_19196_amd", "csrc", f), "rb").read()
                        for f in rec["sources"])
-        lf = dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2), tile_width=pf.tile_width or 8)
+        lf = dict(kbuf=pf.kbuf or 48, persistent=bool(pf.flags & 2), tile_width=pf.tile_width or 8)
         if rec.get("kernel_sources_sha256") == hashlib.sha256(src).hexdigest() and rec.get("workload") == w["name"] \
-                and (dom == "bwd" or rec.get("launch_fwd") == lf):
+                and rec.get("hit_list") == base.hit_list and (dom == "bwd" or rec.get("launch_fwd") == lf):
             traffic = rec[f"render_{dom}_bytes"]
     except (OSError, KeyError, ValueError):
         traffic = None
 
+    # ---- achievable HBM bandwidth: a 1 GiB device copy (read + write)
+    def copy_gbs():
+        nf = 1 << 28
+        a = torch.empty(nf, dtype=torch.float32, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        best = float("inf")
+        for _ in range(5):
+            e0, e1 = ev(), ev()
+            e0.record()
+            b.copy_(a)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        del a, b
+        return 2.0 * nf * 4 / (best * 1e-3) / 1e9
+
+    copy_bw = copy_gbs()
+    hbm = dict(achieved=round(achieved_hbm, 2), peak=PEAK_HBM_GBS, unit="GB/s",
+               frac=round(achieved_hbm / PEAK_HBM_GBS, 6), compulsory_bytes=int(comp_bytes),
+               copy_gbs=round(copy_bw, 1), frac_of_copy=round(achieved_hbm / copy_bw, 6),
+               counter_bytes=traffic,
+               counter_gbs=round(traffic / (dom_ms * 1e-3) / 1e9, 1) if traffic else None,
+               counter_frac=round(traffic / (dom_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 5) if traffic else None,
+               waste=round(traffic / comp_bytes, 2) if traffic else None)
+    alu = dict(achieved=round(achieved_alu, 3), peak=PEAK_FP32_TFLOPS, unit="TFLOP/s",
+               frac=round(achieved_alu / PEAK_FP32_TFLOPS, 4), algorithmic_flops=float(dom_flops))
+    # the nearer of the two roofs bounds the kernel
+    bound = "hbm" if hbm["frac"] >= alu["frac"] else "alu"
+    top = hbm if bound == "hbm" else alu
+    roofline = {"bound": bound, "kernel": f"render_{dom}", "achieved": top["achieved"], "peak": top["peak"],
+                "unit": top["unit"], "frac": top["frac"], "traffic": traffic, "kernel_ms": round(dom_ms, 4),
+                "hbm": hbm, "alu": alu}
+
+    # ---- batched persistent launch vs one launch per view
+    batching = None
+    if not args.no_batching and mesh_np is None:
+        try:
+            batching = batching_comparison(R, dev, args, ev, timed, graph_of, log)
+        except Exception as e:  # reported, never fatal for the headline
+            log(f"batching comparison failed: {e!r}")
+            batching = {"error": repr(e)}
+
     # ---- parity on a seeded sample of pixels against the FP64 oracle, and the oracle's own rate
+    step()
+    torch.cuda.synchronize()
     err = None
     cpu = None
     try:
@@ -364,7 +471,9 @@ def main():
             else:
                 ref, _, _ = O.render_fwd(sc, o[sel], d[sel], op)
                 res = O.compare_with_alternatives(out_h[sel], ref, sc, o[sel], d[sel], op, tol=1e-4)
-                err = dict(max_abs_rgb=res["max_err"], within_1e4=res["within"], resolved=res["resolved"],
+                e_abs = np.abs(out_h[sel] - ref).max(axis=1)
+                err = dict(max_abs_rgb=res["max_err"], p9999_abs_rgb=float(np.quantile(e_abs, 0.9999)),
+                           within_1e4=res["within"], resolved=res["resolved"],
                            unresolved=len(res["unresolved"]), sampled=int(args.parity_rays))
         if not args.no_cpu_baseline:
             sel = np.sort(rng.choice(nr, args.cpu_rays, replace=False))
@@ -387,6 +496,7 @@ def main():
     except Exception as e:  # the oracle is optional on the GPU machine
         log(f"oracle leg skipped: {e}")
 
+    pool_slots = base.hit_list * nr
     line = {
         "metric": METRIC,
         "value": round(mrays_fb, 3),
@@ -403,12 +513,12 @@ def main():
         "config": {"workload": w["name"], "gaussians": n, "rays": nr, "views": len(views),
                    "mesh_triangles": mesh_np.n_tris if mesh_np is not None else 0,
                    "mesh_bounces": shading.max_bounces if shading is not None else 0,
-                   "step": "bvh+fwd+L1+bwd", "graph": ms_graph is not None, "hit_list": base.hit_list,
+                   "step": "bvh+fwd+L1+bwd", "graph": not args.no_graph, "hit_list": base.hit_list,
                    "gradient": f"paper (eps2 {args.eps2:g})" if args.paper_gradient else "exact",
                    "loss": "mean L1" if args.loss == "l1" else "0.8 L2 + 0.2 D-SSIM (11x11, sigma 1.5)",
-                   "launch_fwd": dict(kbuf=pf.kbuf or 24, persistent=bool(pf.flags & 2),
+                   "launch_fwd": dict(kbuf=pf.kbuf or 48, persistent=bool(pf.flags & 2),
                                       tile_width=pf.tile_width or 8),
-                   "launch_bwd": dict(kbuf=pb.kbuf or 24, persistent=bool(pb.flags & 2),
+                   "launch_bwd": dict(kbuf=pb.kbuf or 48, persistent=bool(pb.flags & 2),
                                       tile_width=pb.tile_width or 8)},
         "fwd_mrays_s": round(mrays_f, 3),
         "render_only_fwd_mrays_s": round(mrays_render, 3),
@@ -416,12 +526,15 @@ def main():
         "eager_ms_per_step": round(ms_eager, 4),
         "eager_ms_fwd_step": round(ms_fwd_eager, 4),
         "kernel_ms_median": {k: round(v, 4) for k, v in med.items()},
-        "roofline": {"bound": "alu", "kernel": f"render_{dom}", "achieved": round(achieved, 3), "peak": 157.3,
-                     "unit": "TFLOP/s", "frac": round(achieved / 157.3, 4), "traffic": traffic,
-                     "algorithmic_flops": float(dom_flops)},
-        "work_per_ray": {k: round(v / nr, 2) for k, v in cf.items() if v},
-        "work_per_ray_bwd": {("list_packets" if k == "r9" else "list_composited" if k == "r10" else
-                              "list_grad_groups" if k == "r11" else k): round(v / nr, 3) for k, v in cb.items() if v},
+        "recompute": recompute,
+        "roofline": roofline,
+        "work_per_ray": {k: round(v / nr, 3) for k, v in cf.items() if v},
+        "work_per_ray_bwd": {k: round(v / nr, 3) for k, v in cb.items() if v},
+        "hit_lists": dict(pool_slots_per_ray=base.hit_list,
+                          rows_per_packet=round(cf["list_rows"] / max(cf["packets"], 1), 2),
+                          slots_used_frac=round(cf["list_rows"] * 64 / max(pool_slots, 1), 4) if lists else None,
+                          ray_state_bytes=R.state_bytes(nr, base),
+                          pool_exhausted=bool(cb["adjoint_packets"] > 0) if lists else None),
         "autotune": tune,
         "batching": batching,
         "device_status": status,
@@ -429,6 +542,97 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def batching_comparison(R, dev, args, ev, timed, graph_of, log):
+    """Forward and forward+backward of the 8-view batch (300k Gaussians, 4 x
+    800x800 + 4 x 400x300) and of the mesh workload's primary rays (500k
+    Gaussians, 4 x 1024x768) in two forms on the same GPU: one persistent launch
+    over all views, and one plain launch per view. Each form is captured in a HIP
+    graph and replayed; HBM fractions are compulsory bytes over the time."""
+    import numpy as np
+    import torch
+
+    from synthetic import workload
+    from synthetic.cameras import concat_rays
+
+    res = {}
+    for k in (3, 5):
+        t0 = time.time()
+        w = workload(k)
+        sc = w["scene"]
+        o, d, views = concat_rays(w["cams"])
+        views = [tuple(int(x) for x in v) for v in views]
+        name = w["name"] + (" (primary rays)" if k == 5 else "")
+        nr, n = o.shape[0], sc.n
+        tt = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        g = R.Gaussians(*(tt(a) for a in sc.arrays()))
+        rays = R.Rays(tt(o), tt(d), views=views)
+        per_rays = [R.Rays(rays.origin[off:off + vw * vh], rays.direction[off:off + vw * vh], views=[(0, vw, vh)])
+                     for off, vw, vh in views]
+        hl = args.hit_list
+        pb_ = R.Params(flags=2, hit_list=hl)   # one persistent launch over every view
+        pv_ = R.Params(hit_list=hl)            # one plain launch per view
+        ws = torch.empty(R.workspace_bytes(n), dtype=torch.uint8, device=dev)
+        bvh = R.build_bvh(g, pb_, workspace=ws)
+        out = torch.empty((nr, 3), dtype=torch.float32, device=dev)
+        tgt = torch.rand((nr, 3), dtype=torch.float32, device=dev, generator=torch.Generator(device=dev).manual_seed(k))
+        st_b = R.new_state(nr, pb_, dev)
+        st_v = [R.new_state(r.n, pv_, dev) for r in per_rays]
+        gr_b = tuple(torch.empty_like(x) for x in (g.mean, g.scale, g.quat, g.opacity, g.rgb))
+        gr_v = [tuple(torch.empty_like(x) for x in (g.mean, g.scale, g.quat, g.opacity, g.rgb)) for _ in views]
+
+        def fwd_b():
+            R.render_fwd(bvh, g, rays, pb_, out=out, state=st_b)
+
+        def fb_b():
+            fwd_b()
+            R.render_bwd(bvh, g, rays, pb_, torch.sign(out - tgt) * (1.0 / (3.0 * nr)), st_b, grads=gr_b)
+
+        def fwd_v():
+            for (off, vw, vh), r, s in zip(views, per_rays, st_v):
+                R.render_fwd(bvh, g, r, pv_, out=out[off:off + vw * vh], state=s)
+
+        def fb_v():
+            fwd_v()
+            gr = torch.sign(out - tgt) * (1.0 / (3.0 * nr))
+            for (off, vw, vh), r, s, gv in zip(views, per_rays, st_v, gr_v):
+                R.render_bwd(bvh, g, r, pv_, gr[off:off + vw * vh], s, grads=gv)
+
+        # forward images of the two forms are the same bit for bit
+        fwd_b()
+        img_b = out.clone()
+        fwd_v()
+        same = bool(torch.equal(img_b, out))
+        # compulsory bytes from the counted forward's composited hits
+        qc = dataclasses.replace(pb_, flags=pb_.flags | 8)
+        bvh_c = R.build_bvh(g, qc, workspace=ws)
+        R.render_fwd(bvh_c, g, rays, qc, out=out, state=st_b)
+        comp = R.read_counters(bvh_c)["lane_composited"]
+        bvh = R.build_bvh(g, pb_, workspace=ws)
+        fb_bytes = compulsory_fwd(nr, n, comp, hl > 0)
+        fbb_bytes = fb_bytes + compulsory_bwd(nr, n, comp, hl > 0)
+        row = dict(gaussians=n, rays=nr, views=len(views), identical_forward=same)
+        for form, f_fwd, f_fb in (("batched_persistent", fwd_b, fb_b), ("per_view", fwd_v, fb_v)):
+            for _ in range(2):
+                f_fb()
+            ga, gb = graph_of(f_fwd), graph_of(f_fb)
+            ms_f, _ = timed(ga.replay, args.steps)
+            ms_fb, _ = timed(gb.replay, args.steps)
+            del ga, gb
+            row[form] = dict(fwd_ms=round(ms_f, 4), fwd_bwd_ms=round(ms_fb, 4),
+                             fwd_mrays_s=round(nr / (ms_f * 1e-3) / 1e6, 2),
+                             fwd_bwd_mrays_s=round(nr / (ms_fb * 1e-3) / 1e6, 2),
+                             fwd_hbm_frac=round(fb_bytes / (ms_f * 1e-3) / 1e9 / PEAK_HBM_GBS, 6),
+                             fwd_bwd_hbm_frac=round(fbb_bytes / (ms_fb * 1e-3) / 1e9 / PEAK_HBM_GBS, 6))
+        row["speedup_fwd"] = round(row["per_view"]["fwd_ms"] / row["batched_persistent"]["fwd_ms"], 3)
+        row["speedup_fwd_bwd"] = round(row["per_view"]["fwd_bwd_ms"] / row["batched_persistent"]["fwd_bwd_ms"], 3)
+        row["status"] = R.read_status(bvh)
+        res[name] = row
+        log(f"batching {name}: {row} ({time.time() - t0:.1f}s)")
+        del g, rays, per_rays, ws, out, st_b, st_v, gr_b, gr_v, bvh, bvh_c
+        torch.cuda.empty_cache()
+    return res
 
 
 if __name__ == "__main__":

@@ -53,7 +53,8 @@ enum {
     RS_ERR_BVH_MISMATCH = -4,    /* BVH built for another scene size or Q */
     RS_ERR_STACK_OVERFLOW = -5,  /* device: traversal stack deeper than stack_depth */
     RS_ERR_NONFINITE = -6,       /* device: a non-finite or out-of-range Gaussian parameter */
-    RS_ERR_UNSUPPORTED = -7      /* valid but unsupported combination (e.g. too many views) */
+    RS_ERR_UNSUPPORTED = -7,     /* valid but unsupported combination (e.g. too many views) */
+    RS_ERR_LIST_POOL = -8        /* device: the paper variant's stored-list pool ran out */
 };
 
 /* ------------------------------------------------------------------- flags */
@@ -67,7 +68,9 @@ enum {
                                       eps1 stop the forward keeps the ids of the next hits
                                       while their transmittance stays >= eps2 (image unchanged),
                                       and the last composited Gaussian's gradient sees them
-                                      instead of the background. Needs 0 < max_hits <= hit_list.
+                                      instead of the background. Needs 0 < max_hits and
+                                      hit_list > 0; a pool of max_hits + 64 slots per ray
+                                      never runs out (RS_ERR_LIST_POOL otherwise).
                                       Not for the mesh renders. */
 
 #define RS_BUILD_LBVH   (1u << 5)  /* rs_build_bvh: link the Morton-sorted leaves as a binary radix
@@ -116,11 +119,14 @@ typedef struct {
  * pixels of the 64-ray packet tile of a view (4, 8, 16 or 32, i.e. 4x16, 8x8,
  * 16x4 or 32x2 pixels; 0 = 8); like kbuf it changes the time, not the result.
  * hit_list: store-or-recompute choice of the adjoint (0..4096; 0 = recompute):
- * with C > 0 the forward also records, per ray, the ids of the first C
- * Gaussians it composites (4 C bytes per ray of ray state) and the adjoint
- * replays those lists instead of traversing the BVH again; a ray that
- * composites more than C hits replays its C stored hits and traverses only for
- * the hits after them. The gradients are the same (up to float atomic order). The mesh renders keep their lists in the frame. */
+ * with C > 0 the forward also records the ids of the Gaussians each ray
+ * composites, in a pool of C 4-byte slots per ray on average inside the ray
+ * state (a packet of 64 rays takes one row of 64 slots per compositing step of
+ * its wavefront, from chunks of 16 rows), and the adjoint replays those lists
+ * instead of traversing the BVH again. The rays of a packet that finds the pool
+ * exhausted are traversed again by the adjoint. The gradients are the same (up to
+ * float atomic order). The mesh renders keep one pool for all their ray sets in
+ * the frame. */
 typedef struct {
     float Q, eps1, t_min;
     int32_t max_hits;
@@ -152,9 +158,13 @@ void rs_default_params(rs_params *p);
 /* Device workspace needed to build and keep a BVH over n Gaussians. */
 size_t rs_bvh_workspace_bytes(int64_t n_gaussians);
 
-/* Per-ray state written by rs_render_fwd and read by rs_render_bwd: 16 bytes
- * per ray (composited colour, final transmittance) and, when p->hit_list = C
- * > 0, a hit count and C Gaussian ids per ray (p may be NULL: C = 0). */
+/* Per-ray state written by rs_render_fwd and read by rs_render_bwd (p may be
+ * NULL: C = 0). Its first 16 n bytes are float32 [n][4]: the final colour
+ * (composite + T background) and the final transmittance T of each ray. Then
+ * 16 bytes per ray that the adjoint starts from (the last composited hit and
+ * where T reached 0) and, when p->hit_list = C > 0, 16 bytes of list
+ * bookkeeping per ray plus the stored-list pool (C slots of 4 bytes per ray on
+ * average, in whole chunks of 4 KiB, after a 256-byte header). */
 size_t rs_ray_state_bytes(int64_t n_rays, const rs_params *p);
 
 /* Build the BVH: 30-bit Morton codes of the means, LDS radix sort, leaf boxes
@@ -178,32 +188,39 @@ int rs_build_bvh(const rs_gaussians *g, const rs_params *p, void *ws, size_t ws_
  *  bvh        from rs_build_bvh over the same scene size and Q
  *  out_rgb    device float32 [rays->n][3], written
  *  ray_state  device buffer of rs_ray_state_bytes(rays->n, p) bytes, 16-byte
- *             aligned (256-byte with p->hit_list > 0), written; needed by
- *             rs_render_bwd (may be NULL when no backward pass follows) */
+ *             aligned, written; needed by rs_render_bwd (may be NULL when no
+ *             backward pass follows). The caller must pass a buffer of that
+ *             size: the call takes no size. */
 int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
                   float *out_rgb, void *ray_state, void *stream);
 
-/* Adjoint render (App. A.3-A.6): replays each ray's hits front to back, from
- * its stored hit list (p->hit_list > 0) or by traversing the BVH again, and
- * accumulates d/dtheta sum_k <grad_rgb[k], C_k> into `out` with
- * float32 atomics, aggregated per wave by Gaussian. Must use the same bvh, scene, rays and
- * params (hit_list included) as the forward call that wrote ray_state.
- * grad_rgb: device float32 [rays->n][3]. */
+/* Adjoint render (App. A.3-A.6): walks each ray's composited hits back to
+ * front, from its stored hit list (p->hit_list > 0) or by traversing the BVH
+ * again from the last composited hit, builds the colour S_{k+1} seen behind
+ * each hit from the background forward (dL/dalpha_k = T_k <g, c_k - S_{k+1}>,
+ * no division by 1 - alpha_k), and accumulates d/dtheta sum_k <grad_rgb[k], C_k>
+ * into `out` with float32 atomics, aggregated per wave by Gaussian. Must use the
+ * same bvh, scene, rays and params (hit_list included) as the forward call that
+ * wrote ray_state. grad_rgb: device float32 [rays->n][3]. */
 int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, const rs_params *p,
                   const float *grad_rgb, const void *ray_state, rs_grads *out, void *stream);
 
 /* Synchronise `stream` and return the sticky device status of this BVH's
- * workspace (RS_OK, RS_ERR_STACK_OVERFLOW or RS_ERR_NONFINITE). */
+ * workspace (RS_OK, RS_ERR_STACK_OVERFLOW, RS_ERR_NONFINITE or
+ * RS_ERR_LIST_POOL): what the last rs_build_bvh found in the inputs and what
+ * every render and adjoint call since then found (a build clears it). */
 int rs_read_status(const rs_bvh *bvh, void *stream);
 
 /* Synchronise `stream` and copy the work counters accumulated by render calls
- * made with RS_COUNTERS since the last rs_build_bvh (host uint64 out[12]):
- * [0] ray packets, [1] inner-node visits, [2] leaf visits, [3] traversal
- * rounds (all per wavefront), [4] lane leaf tests on live rays, [5] hits
- * entering a lane's buffer, [6] composited hits, [7] lane child-box overlaps,
- * [8] adjoint: per-wave gradient groups (distinct Gaussians per slot),
- * stored-list adjoint: [9] ray packets, [10] composited hits, [11] gradient
- * groups.
+ * made with RS_COUNTERS since the last rs_build_bvh (host uint64 out[16]):
+ * [0] forward ray packets, [1] inner-node visits, [2] leaf visits, [3]
+ * traversal rounds (all per wavefront), [4] lane leaf tests on live rays, [5]
+ * hits entering a lane's buffer, [6] forward: hits consumed (composited, or
+ * collected by the paper variant), traversal adjoint: hits differentiated, [7]
+ * lane child-box overlaps, [8] traversal adjoint: per-wave gradient groups
+ * (distinct Gaussians per step), stored-list adjoint: [9] ray packets, [10]
+ * differentiated hits, [11] gradient groups; [12] stored-list rows appended
+ * by the forward, [13] traversal adjoint packets, [14], [15] unused.
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 
@@ -296,9 +313,9 @@ int rs_trace_mesh(const rs_bvh *mesh_bvh, const rs_rays *rays, const float *t_li
 
 /* Per-frame device scratch of the mesh render for n rays (the path and shadow
  * rays of every level, their states, the terms the adjoint needs and, with
- * p->hit_list = C > 0, the stored hit lists of the 2B + 1 ray sets:
- * (2B + 1)(C + 1) 4 bytes per ray), 256-byte aligned. p may be NULL (C = 0);
- * sh may be NULL (B = 1). */
+ * p->hit_list = C > 0, one stored-list pool for the 2B + 1 ray sets of
+ * (2B + 1) C slots of 4 bytes per ray), 256-byte aligned. p may be NULL
+ * (C = 0); sh may be NULL (B = 1). */
 size_t rs_mesh_frame_bytes(int64_t n_rays, const rs_params *p, const rs_shading *sh);
 
 /* Forward render of Gaussians + mesh with path and shadow rays. After the
@@ -350,6 +367,18 @@ int rs_loss(const float *img, const float *target, int32_t width, int32_t height
 
 /* Human-readable text of a status code (static string). */
 const char *rs_status_string(int code);
+
+/* Copy the stored hit lists of a ray state written by rs_render_fwd (with the
+ * same rays and params, p->hit_list > 0) to host memory; synchronises
+ * `stream`. Inspection helper for tests and tools, not part of the method.
+ *  count[n]   hits each ray composited
+ *  stored[n]  how many of them its list holds (fewer when the pool ran out)
+ *  extra[n]   ids the paper variant collected after the eps1 stop, else 0
+ *  ids        [n][cap]: per ray its stored ids in compositing order, then the
+ *             collected ones; -1 after the last (entries beyond cap dropped)
+ * Any output pointer may be NULL (ids needs cap > 0). */
+int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, int32_t *count,
+                          int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap, void *stream);
 
 /* Copy the built BVH to host memory for inspection (synchronises `stream`).
  * Any pointer may be NULL. codes[n] (uint32, sorted Morton codes),

@@ -2,6 +2,9 @@
 // the build and render launchers.
 #include <string.h>
 
+#include <unordered_map>
+#include <vector>
+
 #include "rs_internal.h"
 
 using namespace rs;
@@ -30,10 +33,18 @@ static int check_params(const rs_params *p)
         return RS_ERR_INVALID_ARG;
     if (p->hit_list < 0 || p->hit_list > 4096) return RS_ERR_INVALID_ARG;
     if (p->flags & RS_PAPER_GRADIENT) {
-        // the second phase lives in the stored lists, which must never overflow
+        // the second phase lives in the stored lists: K_max bounds a ray's entries
         if (!(p->eps2 >= 0.0f && p->eps2 <= 1.0f)) return RS_ERR_INVALID_ARG;
-        if (p->max_hits <= 0 || p->hit_list < p->max_hits) return RS_ERR_INVALID_ARG;
+        if (p->max_hits <= 0 || p->hit_list <= 0) return RS_ERR_INVALID_ARG;
     }
+    return RS_OK;
+}
+
+// the list pool's chunk counter and chunk indices are 31-bit
+static int check_pool(int64_t n_rays, const rs_params *p, int64_t sets)
+{
+    if (p->hit_list > 0 && list_chunks(n_rays * int64_t(p->hit_list) * sets) >= (int64_t(1) << 31))
+        return RS_ERR_UNSUPPORTED;
     return RS_OK;
 }
 
@@ -121,7 +132,8 @@ int rs_render_fwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
     BvhDesc D;
     if ((e = check_bvh(bvh, g, p, D))) return e;
     if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
-    if (ray_state && !aligned(ray_state, p->hit_list > 0 ? 256 : 16)) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    if ((e = check_pool(rays->n, p, 1))) return e;
     return launch_render(D, g, rays, p, out_rgb, ray_state, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
@@ -135,8 +147,8 @@ int rs_render_bwd(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays,
     BvhDesc D;
     if ((e = check_bvh(bvh, g, p, D))) return e;
     if (!out) return RS_ERR_INVALID_ARG;
-    if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, p->hit_list > 0 ? 256 : 16)))
-        return RS_ERR_INVALID_ARG;
+    if (rays->n > 0 && (!grad_rgb || !ray_state || !aligned(ray_state, 16))) return RS_ERR_INVALID_ARG;
+    if ((e = check_pool(rays->n, p, 1))) return e;
     return launch_render(D, g, rays, p, nullptr, const_cast<void *>(ray_state), grad_rgb, out,
                          static_cast<hipStream_t>(stream));
 }
@@ -238,6 +250,7 @@ int rs_render_mesh_fwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
     if ((e = check_bvh(gauss_bvh, g, p, G))) return e;
     if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
     if (rays->n > 0 && (!out_rgb || !frame || !aligned(frame, 256))) return RS_ERR_INVALID_ARG;
+    if ((e = check_pool(rays->n, p, 2 * sh->max_bounces + 1))) return e;
     return launch_mesh_fwd(G, M, g, sh, rays, p, out_rgb, frame, static_cast<hipStream_t>(stream));
 }
 
@@ -257,6 +270,7 @@ int rs_render_mesh_bwd(const rs_bvh *gauss_bvh, const rs_bvh *mesh_bvh, const rs
     if ((e = check_mesh_bvh(mesh_bvh, m, M))) return e;
     if (!out) return RS_ERR_INVALID_ARG;
     if (rays->n > 0 && (!grad_rgb || !frame || !aligned(frame, 256))) return RS_ERR_INVALID_ARG;
+    if ((e = check_pool(rays->n, p, 2 * sh->max_bounces + 1))) return e;
     return launch_mesh_bwd(G, g, sh, rays, p, grad_rgb, frame, out, static_cast<hipStream_t>(stream));
 }
 
@@ -273,6 +287,7 @@ int rs_read_status(const rs_bvh *bvh, void *stream)
     if (hipMemcpy(&s, D.ws + L.header, sizeof(s), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     if (s & kStatusStack) return RS_ERR_STACK_OVERFLOW;
     if (s & kStatusNonfinite) return RS_ERR_NONFINITE;
+    if (s & kStatusListPool) return RS_ERR_LIST_POOL;
     return RS_OK;
 }
 
@@ -286,7 +301,7 @@ int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream)
     WsHeader h;
     Layout L = make_layout(D.n);
     if (hipMemcpy(&h, D.ws + L.header, sizeof(h), hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
-    for (int k = 0; k < 12; ++k) out[k] = h.counters[k];
+    for (int k = 0; k < 16; ++k) out[k] = h.counters[k];
     return RS_OK;
 }
 
@@ -303,7 +318,8 @@ int rs_autotune(const rs_bvh *bvh, const rs_gaussians *g, const rs_rays *rays, c
     if (!result || reps < 1 || reps > 100) return RS_ERR_INVALID_ARG;
     if (rays->n > 0 && !out_rgb) return RS_ERR_INVALID_ARG;
     if (grad_rgb && (!ray_state || !grads)) return RS_ERR_INVALID_ARG;
-    if (ray_state && !aligned(ray_state, base->hit_list > 0 ? 256 : 16)) return RS_ERR_INVALID_ARG;
+    if (ray_state && !aligned(ray_state, 16)) return RS_ERR_INVALID_ARG;
+    if ((e = check_pool(rays->n, base, 1))) return e;
     memset(result, 0, sizeof(*result));
     hipStream_t st = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
@@ -397,6 +413,7 @@ const char *rs_status_string(int code)
     case RS_ERR_STACK_OVERFLOW: return "traversal stack overflow";
     case RS_ERR_NONFINITE: return "non-finite or out-of-range Gaussian parameter";
     case RS_ERR_UNSUPPORTED: return "unsupported configuration";
+    case RS_ERR_LIST_POOL: return "stored hit-list pool exhausted (paper gradient variant)";
     default: return "unknown status";
     }
 }
@@ -442,6 +459,81 @@ int rs_bvh_download(const rs_bvh *bvh, uint32_t *codes, int32_t *perm, int32_t *
                 for (int k = 0; k < 12; ++k) boxes[12 * i + k] = tmp[16 * i + k];
         }
         delete[] tmp;
+    }
+    return RS_OK;
+}
+
+// Lane of ray r inside its 64-ray packet (the tile layout of rs_render_fwd).
+static int ray_lane(const rs_rays *rays, int tile_shift, int64_t r)
+{
+    if (rays->n_views == 0) return int(r % kWave);
+    for (int v = 0; v < rays->n_views; ++v) {
+        const rs_view &V = rays->views[v];
+        const int64_t local = r - V.ray_offset;
+        if (local < 0 || local >= int64_t(V.width) * V.height) continue;
+        const int64_t y = local / V.width, x = local - y * V.width;
+        const int tw = 1 << tile_shift, th = kWave >> tile_shift;
+        return int((y % th) * tw + (x % tw));
+    }
+    return 0;
+}
+
+int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, int32_t *count,
+                          int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap, void *stream)
+{
+    int e = check_rays(rays);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if (!ray_state || p->hit_list <= 0 || cap < 0 || (ids && cap == 0)) return RS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RS_ERR_HIP;
+    const int64_t n = rays->n;
+    if (n == 0) return RS_OK;
+    const StateLayout SL = state_layout(n, p->hit_list);
+    const char *base = static_cast<const char *>(ray_state);
+    std::vector<int4> li(static_cast<size_t>(n));
+    if (hipMemcpy(li.data(), base + SL.list, size_t(n) * 16, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+    ListPool P = list_pool_at(const_cast<char *>(base) + SL.pool, SL.chunks);
+    unsigned long long taken = 0;
+    if (hipMemcpy(&taken, P.hdr, 8, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+    const int64_t used = int64_t(taken < (unsigned long long)P.chunks ? taken : (unsigned long long)P.chunks);
+    std::vector<int32_t> prev(size_t(used > 0 ? used : 1));
+    std::vector<uint32_t> slots(size_t(used > 0 ? used : 1) * kListRows * kWave);
+    if (used > 0) {
+        if (hipMemcpy(prev.data(), P.prev, size_t(used) * 4, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
+        if (hipMemcpy(slots.data(), P.slots, size_t(used) * kListRows * kWave * 4, hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return RS_ERR_HIP;
+    }
+    const int ts = tile_shift_of(p);
+    std::unordered_map<int32_t, std::vector<int32_t>> chains;  // a packet's chunks, first to last
+    for (int64_t r = 0; r < n; ++r) {
+        const int4 L = li[size_t(r)];
+        if (count) count[r] = L.x;
+        if (stored) stored[r] = L.y;
+        int32_t x = 0, w = 0;
+        if (L.w > 0 && L.z >= 0 && L.z < used) {
+            auto it = chains.find(L.z);
+            if (it == chains.end()) {
+                std::vector<int32_t> ch;
+                for (int32_t c = L.z; c >= 0 && c < used && int64_t(ch.size()) <= used; c = prev[size_t(c)])
+                    ch.push_back(c);
+                std::vector<int32_t> fw(ch.rbegin(), ch.rend());
+                it = chains.emplace(L.z, std::move(fw)).first;
+            }
+            const std::vector<int32_t> &ch = it->second;
+            const int lane = ray_lane(rays, ts, r);
+            for (int32_t row = 0; row < L.w && size_t(row / kListRows) < ch.size(); ++row) {
+                const uint32_t v =
+                    slots[(size_t(ch[size_t(row / kListRows)]) * kListRows + size_t(row % kListRows)) * kWave + lane];
+                if (v == kListIdle) continue;
+                if (v & kListSecond) ++x;
+                if (ids && w < cap) ids[r * int64_t(cap) + w] = int32_t(v & ~kListSecond);
+                ++w;
+            }
+        }
+        if (ids)
+            for (int32_t k = w; k < cap; ++k) ids[r * int64_t(cap) + k] = -1;
+        if (extra) extra[r] = x;
     }
     return RS_OK;
 }

@@ -20,7 +20,7 @@ __global__ void k_init_header(WsHeader *h)
     if (threadIdx.x == 0) {
         h->status = 0;
         h->queue = 0;
-        for (int k = 0; k < 12; ++k) h->counters[k] = 0;
+        for (int k = 0; k < 16; ++k) h->counters[k] = 0;
         for (int k = 0; k < 3; ++k) {
             h->bounds[k] = 0xffffffffu;
             h->bounds[3 + k] = 0u;

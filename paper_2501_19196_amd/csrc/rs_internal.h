@@ -59,6 +59,7 @@ inline int ploc_cap(int64_t n) { return 256 + 10 * ploc_halvings(n); }
 // Device status bits (sticky, OR-ed by kernels).
 constexpr int kStatusStack = 1;
 constexpr int kStatusNonfinite = 2;
+constexpr int kStatusListPool = 4;  // RS_PAPER_GRADIENT: the stored-list pool ran out
 
 // Gaussian record, one per sorted position (64 bytes, four float4):
 //   r0 = (RT00, RT01, RT02, RT10), r1 = (RT11, RT12, RT20, RT21),
@@ -75,9 +76,9 @@ struct WsHeader {
     uint32_t queue;        // persistent packet counter
     uint32_t bounds[6];    // ordered-uint min xyz, max xyz of the means
     float root_box[6];
-    uint64_t counters[12];  // instrumentation (RS_COUNTERS)
+    uint64_t counters[16];  // instrumentation (RS_COUNTERS)
     uint32_t xq[8];         // persistent packet counters, one per XCD chunk
-    uint32_t pad[18];
+    uint32_t pad[10];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
@@ -164,39 +165,113 @@ __device__ inline float ordered_to_float(uint32_t u)
     return __uint_as_float(b);
 }
 
+// Ray state of one ray set (caller-owned), 256-byte aligned sections:
+//   fin[n]   float4: final colour (composite + T bg) and final transmittance T
+//   last[n]  uint4: the last composited hit's key (low word: Gaussian index,
+//            high word: float bits of t1 + bias; both 0 when nothing was
+//            composited), then T just before the hit that took T below the
+//            smallest normal float (to 0 when alpha = 1) and the number of
+//            composited hits after that one (0xffffffff when T stayed normal).
+//            The adjoint walks the hits back to front from that key and
+//            recovers T_k = T_{k+1} / (1 - alpha_k) from the final T; the saved
+//            T restarts the recursion where it would divide 0 by 0 or lose its
+//            digits in the subnormals.
+//   list[n]  int4 (only with stored hit lists): composited hits, how many of
+//            them the pool holds, the ray's packet's last pool chunk and its
+//            stored row count.
+struct SetState {
+    float4 *fin;
+    uint4 *last;
+    int4 *list;
+};
+
+// Stored hit lists: one pool shared by every packet of a launch. A packet's
+// wavefront appends one row of 64 slots (one per lane: the Gaussian index it
+// composited at that step, the index | kListSecond for a hit it only collected
+// in the paper variant's second phase, kListIdle otherwise) per compositing
+// step; rows live in chunks of kListRows, linked backwards per packet. The
+// pool header holds the chunk counter (64-bit) and a flag set when a packet
+// found the pool exhausted (its later rows are not stored).
+constexpr int kListRows = 16;
+constexpr uint32_t kListIdle = 0xffffffffu;
+constexpr uint32_t kListSecond = 0x80000000u;
+struct ListPool {
+    unsigned long long *hdr;  // [0] chunks taken, [1] exhausted flag
+    int32_t *prev;            // [chunks] previous chunk of the same packet (-1: first)
+    uint32_t *slots;          // [chunks][kListRows][64]
+    int64_t chunks;
+};
+inline int64_t list_chunks(int64_t slots_wanted)
+{
+    return (slots_wanted + int64_t(kListRows) * 64 - 1) / (int64_t(kListRows) * 64);
+}
+// bytes of a pool of `chunks` chunks (header, links, slots), 256-byte aligned
+inline size_t list_pool_bytes(int64_t chunks)
+{
+    if (chunks <= 0) return 0;
+    return 256 + align256(size_t(chunks) * 4) + size_t(chunks) * kListRows * 64 * 4;
+}
+inline ListPool list_pool_at(char *base, int64_t chunks)
+{
+    ListPool P{nullptr, nullptr, nullptr, 0};
+    if (!base || chunks <= 0) return P;
+    P.hdr = reinterpret_cast<unsigned long long *>(base);
+    P.prev = reinterpret_cast<int32_t *>(base + 256);
+    P.slots = reinterpret_cast<uint32_t *>(base + 256 + align256(size_t(chunks) * 4));
+    P.chunks = chunks;
+    return P;
+}
+
 // Host description of one ray set of a render launch.
 struct SetDesc {
     const rs_rays *rays;
-    float *out_rgb;
-    void *state;
+    float *out_rgb;   // forward output (may be null in the adjoint)
+    SetState state;   // fin may be null: no state written (forward without adjoint)
     const float *grad;
-    int32_t *count;  // stored hit lists (optional)
-    int32_t *ids;
     float bg[3];
     int32_t zero_colour;
 };
 
-// Ray state: float4 (final colour, final T) per ray; with a hit-list capacity
-// C > 0 it continues (256-byte aligned sections) with int32 count[n] and
-// int32 ids[C][n] (the k-th composited Gaussian of ray r at ids[k][r]).
+// Layout of the caller's ray state for n rays and hit-list capacity C
+// (pool of C slots per ray on average).
 struct StateLayout {
-    size_t count, ids, total;
+    size_t fin, last, list, pool, total;
+    int64_t chunks;
 };
 inline StateLayout state_layout(int64_t n, int32_t cap)
 {
-    StateLayout L{0, 0, 0};
+    StateLayout L{0, 0, 0, 0, 0, 0};
     const size_t nn = size_t(n > 0 ? n : 0);
-    L.total = nn * 16;
+    L.fin = 0;
+    L.last = align256(nn * 16);
+    L.total = L.last + nn * 16;
     if (cap <= 0 || nn == 0) return L;
-    L.count = align256(L.total);
-    L.ids = align256(L.count + nn * 4);
-    L.total = L.ids + nn * size_t(cap) * 4;
+    L.list = align256(L.total);
+    L.pool = align256(L.list + nn * 16);
+    L.chunks = list_chunks(int64_t(nn) * cap);
+    L.total = L.pool + list_pool_bytes(L.chunks);
     return L;
 }
+inline SetState state_at(void *base, int64_t n, int32_t cap)
+{
+    SetState S{nullptr, nullptr, nullptr};
+    if (!base || n <= 0) return S;
+    const StateLayout L = state_layout(n, cap);
+    char *b = static_cast<char *>(base);
+    S.fin = reinterpret_cast<float4 *>(b + L.fin);
+    S.last = reinterpret_cast<uint4 *>(b + L.last);
+    if (L.chunks > 0) S.list = reinterpret_cast<int4 *>(b + L.list);
+    return S;
+}
+
+// What a render launch does.
+enum class Pass { Forward, AdjointList, AdjointTraverse };
 
 int launch_build(const rs_gaussians *g, float Q, bool lbvh, char *ws, hipStream_t st);
-int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets, bool bwd,
-                hipStream_t st, bool list_adjoint = false);
+int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets,
+                const ListPool &pool, Pass pass, hipStream_t st);
+// zero a pool's header (before a forward that stores lists)
+void reset_pool(const ListPool &pool, hipStream_t st);
 int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, const rs_params *p, float *out_rgb,
                   void *state, const float *grad, const rs_grads *grads, hipStream_t st);
 void zero_gacc(const BvhDesc &D, hipStream_t st);

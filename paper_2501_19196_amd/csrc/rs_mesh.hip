@@ -147,30 +147,31 @@ struct PathLevel {
     float *o, *d;        // [n][3] rays (level >= 1)
     float *tmax, *bg;    // [n] Gaussian range, [n][3] background of the forward render
     float *out;          // [n][3] C_k (+ T_k bg when the ray leaves the mesh)
-    float4 *st, *stb;    // forward state; adjoint state (radiance R_k, T_k)
+    SetState st;         // forward state (final colour and T, last key, list bookkeeping)
     float *t;            // [n] closest triangle distance
     int32_t *tri;        // [n] closest triangle (-1 none)
     float *w;            // [n] continuation weight (0: none)
     float *shade;        // [n][3] background of the adjoint: D_k + w R_{k+1} at a hit, bg_k otherwise
     float *g;            // [n][3] upstream gradient (level >= 1)
     float *W;            // [n] path weight
-    int32_t *cnt, *ids;  // stored hit lists
 };
 
 struct ShadowLevel {
     float *o, *d, *tmax;  // rays to the light (t_max = distance)
     float *out;           // [n][3] transmittance in channel 0
-    float4 *st;
+    SetState st;
     float *wd;            // [n] diffuse weight * albedo * (n.l) * intensity (0 when blocked or absent)
     float *tb;            // [n] blocker distance (any hit)
     int32_t *trib;        // [n] blocker (-1 none)
     float *g;             // [n][3] upstream gradient of the transmittance (channel 0)
-    int32_t *cnt, *ids;
 };
 
+// The stored hit lists of all 2B + 1 ray sets share one pool of C slots per ray
+// and set on average.
 struct Frame {
     PathLevel P[RS_MAX_BOUNCES + 1];
     ShadowLevel S[RS_MAX_BOUNCES];
+    ListPool pool;
     int32_t bounces;
     size_t total;
 };
@@ -187,6 +188,13 @@ static Frame frame_layout(char *base, int64_t n, int32_t cap, int bounces)
     };
     const size_t f = size_t(n > 0 ? n : 1) * 4;
     auto fl = [&](size_t k) { return reinterpret_cast<float *>(take(k * f)); };
+    auto state = [&]() {
+        SetState S;
+        S.fin = reinterpret_cast<float4 *>(fl(4));
+        S.last = reinterpret_cast<uint4 *>(fl(4));
+        S.list = cap > 0 ? reinterpret_cast<int4 *>(fl(4)) : nullptr;
+        return S;
+    };
     for (int k = 0; k <= bounces; ++k) {
         PathLevel &L = F.P[k];
         if (k > 0) {
@@ -197,17 +205,12 @@ static Frame frame_layout(char *base, int64_t n, int32_t cap, int bounces)
         L.tmax = fl(1);
         L.bg = fl(3);
         L.out = fl(3);
-        L.st = reinterpret_cast<float4 *>(fl(4));
-        L.stb = reinterpret_cast<float4 *>(fl(4));
+        L.st = state();
         L.t = fl(1);
         L.tri = reinterpret_cast<int32_t *>(fl(1));
         L.w = fl(1);
         L.shade = fl(3);
         L.W = fl(1);
-        if (cap > 0) {
-            L.cnt = reinterpret_cast<int32_t *>(fl(1));
-            L.ids = reinterpret_cast<int32_t *>(fl(size_t(cap)));
-        }
     }
     for (int k = 0; k < bounces; ++k) {
         ShadowLevel &S = F.S[k];
@@ -215,15 +218,16 @@ static Frame frame_layout(char *base, int64_t n, int32_t cap, int bounces)
         S.d = fl(3);
         S.tmax = fl(1);
         S.out = fl(3);
-        S.st = reinterpret_cast<float4 *>(fl(4));
+        S.st = state();
         S.wd = fl(1);
         S.tb = fl(1);
         S.trib = reinterpret_cast<int32_t *>(fl(1));
         S.g = fl(3);
-        if (cap > 0) {
-            S.cnt = reinterpret_cast<int32_t *>(fl(1));
-            S.ids = reinterpret_cast<int32_t *>(fl(size_t(cap)));
-        }
+    }
+    if (cap > 0 && n > 0) {
+        const int64_t chunks = list_chunks(n * int64_t(cap) * (2 * bounces + 1));
+        F.pool = list_pool_at(take(list_pool_bytes(chunks)), chunks);
+        if (!base) F.pool.chunks = chunks;
     }
     F.total = off;
     return F;
@@ -365,7 +369,7 @@ __global__ void k_shadow_prep(const ShadowLevel S, int64_t n)
 
 // Radiance bottom-up: R_B = C_B; R_k = C_k + T_k (D_k + w_k R_{k+1}) at a hit
 // with k < B; pixel = R_0. The shade D_k + w_k R_{k+1} is the background of
-// path ray k's adjoint, and (R_k, T_k) its state.
+// path ray k's adjoint.
 __global__ void k_path_combine(const Frame F, int64_t n, ShadeConst C, float *__restrict__ out_rgb)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -378,7 +382,7 @@ __global__ void k_path_combine(const Frame F, int64_t n, ShadeConst C, float *__
             next = false;
             continue;
         }
-        const float T = L.st[i].w;
+        const float T = L.st.fin[i].w;
         const bool hit = k < F.bounces && L.tri[i] >= 0;
         float sh[3];
         for (int c = 0; c < 3; ++c) sh[c] = L.bg[3 * i + c];
@@ -391,7 +395,6 @@ __global__ void k_path_combine(const Frame F, int64_t n, ShadeConst C, float *__
             R[c] = hit ? __builtin_fmaf(T, sh[c], L.out[3 * i + c]) : L.out[3 * i + c];
             L.shade[3 * i + c] = sh[c];
         }
-        L.stb[i] = make_float4(R[0], R[1], R[2], T);
         next = true;
     }
     for (int c = 0; c < 3; ++c) out_rgb[3 * i + c] = R[c];
@@ -414,7 +417,7 @@ __global__ void k_path_bwd_prep(const Frame F, int64_t n, const float *__restric
             L.g[3 * i + 1] = g1 * W;
             L.g[3 * i + 2] = g2 * W;
         }
-        const float T = active ? L.st[i].w : 0.0f;
+        const float T = active ? L.st.fin[i].w : 0.0f;
         if (k < F.bounces) {
             const ShadowLevel &S = F.S[k];
             const float ws = S.tmax[i] > 0.0f ? W * T * S.wd[i] : 0.0f;
@@ -494,15 +497,11 @@ static int mesh_sets(const Frame &F, const rs_rays *rays, rs_rays *sr, SetDesc *
         sr[m] = frame_rays(rays, k ? L.o : rays->origin, k ? L.d : rays->dir, L.tmax, bwd ? L.shade : L.bg);
         S[m] = SetDesc{};
         S[m].rays = &sr[m];
-        S[m].count = L.cnt;
-        S[m].ids = L.ids;
-        if (bwd) {
-            S[m].state = L.stb;  // the ray's radiance, with the shade as background
-            S[m].grad = k ? L.g : grad;
-        } else {
-            S[m].state = L.st;
+        S[m].state = L.st;
+        if (bwd)
+            S[m].grad = k ? L.g : grad;  // the shade is the background behind the ray's last hit
+        else
             S[m].out_rgb = L.out;
-        }
         ++m;
     }
     for (int k = 0; k < F.bounces; ++k) {
@@ -510,8 +509,6 @@ static int mesh_sets(const Frame &F, const rs_rays *rays, rs_rays *sr, SetDesc *
         sr[m] = frame_rays(rays, H.o, H.d, H.tmax, nullptr);
         S[m] = SetDesc{};
         S[m].rays = &sr[m];
-        S[m].count = H.cnt;
-        S[m].ids = H.ids;
         S[m].state = H.st;
         if (bwd)
             S[m].grad = H.g;
@@ -556,7 +553,7 @@ int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, c
     // 2. Gaussians along all ray sets in one persistent launch
     rs_params ps = *p;
     ps.flags |= RS_PERSISTENT;
-    if ((e = launch_sets(G, g, &ps, nsets, S, false, st))) return e;
+    if ((e = launch_sets(G, g, &ps, nsets, S, F.pool, Pass::Forward, st))) return e;
     // 3. combine bottom-up
     k_path_combine<<<grid_for(n), 256, 0, st>>>(F, n, C, out_rgb);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
@@ -576,14 +573,11 @@ int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *s
         rs_params ps = *p;
         ps.flags |= RS_PERSISTENT;
         int e;
-        if (p->hit_list > 0) {
-            // stored lists of all sets, then traversal for the rays whose list overflowed
-            if ((e = launch_sets(G, g, &ps, nsets, S, true, st, true))) return e;
-            if (p->max_hits == 0 || p->max_hits > p->hit_list)
-                if ((e = launch_sets(G, g, &ps, nsets, S, true, st))) return e;
-        } else {
-            if ((e = launch_sets(G, g, &ps, nsets, S, true, st))) return e;
+        if (F.pool.chunks > 0) {
+            // stored lists of all sets, then traversal for the rays whose list is incomplete
+            if ((e = launch_sets(G, g, &ps, nsets, S, F.pool, Pass::AdjointList, st))) return e;
         }
+        if ((e = launch_sets(G, g, &ps, nsets, S, F.pool, Pass::AdjointTraverse, st))) return e;
     }
     scatter_gacc(G, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;

@@ -14,12 +14,19 @@
 // the K_max and eps1 stops (Sec. 3, "Color Aggregation"). Rounds repeat
 // until every lane has stopped or run out of hits.
 //
-// The adjoint kernel replays the same rounds bit for bit (same code, same
-// operation order) and forms dL/dalpha front to back from the final colour,
-// the quantity the recursion of App. A.4/A.5 carries; the gradients of alpha
-// with respect to the Gaussian parameters follow App. A.6 in a cancellation
-// free form (see grad_hit). Per-Gaussian gradient contributions of a wave are
-// summed across lanes before one set of float32 atomics per Gaussian.
+// The adjoint (App. A.3-A.6) walks each ray's composited hits back to front,
+// either from the forward's stored lists or by traversing the BVH again in
+// rounds that collect the K largest keys below the previous round's first
+// one. The colour seen behind hit k, S_{k+1}, is built back to front
+// (S <- alpha c + (1 - alpha) S from the background), so dL/dalpha_k =
+// T_k <g, c_k - S_{k+1}> needs no division by 1 - alpha_k. T_k comes from the
+// final T as T_{k+1} / (1 - alpha_k) (a relative error of about 2 ulp per
+// hit), restarted from the T the forward saved where T left the normal floats
+// (reached 0 when alpha = 1, or underflowed). The
+// gradients of alpha with respect to the Gaussian parameters follow App. A.6
+// in a cancellation-free form (see grad_hit). Per-Gaussian gradient
+// contributions of a wave are summed across lanes before one set of float32
+// atomics per Gaussian.
 #include <math.h>
 
 #include "rs_device.h"
@@ -44,7 +51,8 @@ struct RenderParams {
     int32_t n_views;
     int32_t tile_shift;
     int32_t strip_tiles;   // persistent: tile strip width of the packet order (0 = row-major)
-    int32_t hit_cap;       // stored hit-list capacity per ray (0 = none)
+    int32_t lists;         // stored hit lists: the forward appends rows, the adjoint replays them
+    int32_t overflow_only; // traversal adjoint next to stored lists: only rays whose list is incomplete
     int32_t paper;         // RS_PAPER_GRADIENT: second phase after an eps1 stop
     float eps2;
     int64_t chunk;         // persistent: packets per XCD queue
@@ -255,16 +263,17 @@ __device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1
     G.v[10] = dLda * __expf(-0.5f * h2);
 }
 
+
 // ----------------------------------------------------------------- kernel
 
 // One set of rays traced by a launch: its rays, optional per-ray limit and
-// background, outputs (forward) or upstream gradient and saved state (adjoint).
+// background, outputs (forward) or upstream gradient (adjoint), and its state.
 struct RaySet {
     const float *origin, *dir, *tmax, *bgray, *grad;
     float *out_rgb;
-    float4 *state;
-    int32_t *count;  // stored hit lists (optional): composited hits per ray
-    int32_t *ids;    // [hit_cap][n_rays] Gaussian ids in compositing order
+    float4 *fin;  // final colour and T
+    uint4 *last;  // last composited key, restart point of the T recursion
+    int4 *list;   // stored-list bookkeeping (hit lists only)
     float bg[3];
     int32_t zero_colour;
 };
@@ -276,6 +285,7 @@ struct Ptrs {
     uint32_t *queue;  // XCD queue counters (kXcdQueues)
     unsigned long long *counters;
     float *gacc;  // adjoint accumulator, 16 floats per Gaussian (see k_scatter_grads)
+    ListPool pool;
 };
 
 // ------------------------------------------------------- shared kernel steps
@@ -383,55 +393,102 @@ __device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__
     return r3.w * __expf(-0.5f * h2);
 }
 
-__device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
-                                     const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
-                                     const RenderParams &P, Accum &A, HitData &H)
+// alpha, colour and test intermediates of a hit (no compositing)
+__device__ inline void recompute_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
+                                     const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc, float Q,
+                                     HitData &H)
 {
-    H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = 0.0f;
+    H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = H.Tk = 0.0f;
     H.g = HitGeom{};
-    H.Tk = A.T;
     if (act) {
-        H.al = hit_alpha(gid, ray, records, inv, P.Q, H.r0, H.r1, H.r2, H.r3, H.t1, H.h2, H.g);
+        H.al = hit_alpha(gid, ray, records, inv, Q, H.r0, H.r1, H.r2, H.r3, H.t1, H.h2, H.g);
         if (!zc) {
             H.cr = rgb[3 * gid];
             H.cg = rgb[3 * gid + 1];
             H.cb = rgb[3 * gid + 2];
         }
-        composite_step(A, H.al, H.cr, H.cg, H.cb);
     }
 }
 
-// Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation: the
-// active lanes' contributions are summed per distinct Gaussian through LDS and
-// one 14-lane segment of an atomic instruction adds each Gaussian's totals to
-// its 64-byte accumulator line (four Gaussians per instruction).
-//   dL/dalpha_k = T_k <g, c_k> - <g, C_out - C_<=k> / (1 - alpha_k); the
-//   remaining colour of the last composited hit is T_final bg, so there
-//   dC/dalpha = T_k (c_k - bg).
+__device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
+                                     const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
+                                     const RenderParams &P, Accum &A, HitData &H)
+{
+    recompute_hit(act, gid, ray, records, inv, rgb, zc, P.Q, H);
+    H.Tk = A.T;
+    if (act) composite_step(A, H.al, H.cr, H.cg, H.cb);
+}
+
+// ------------------------------------------------------- back-to-front adjoint
+
+// Smallest normal float: below it T loses relative precision, so the adjoint does not
+// divide back from there (the forward saves the T before the hit that crossed it).
+constexpr float kMinNormal = 1.17549435e-38f;
+
+// Upstream gradient of a lane's pixel.
 struct LaneGrad {
-    float gr, gg, gb;     // upstream gradient of the pixel
-    float Cor, Cog, Cob;  // final pixel colour (forward state)
+    float gr, gg, gb;
 };
 
+// Back-to-front state of a lane's adjoint: T_{k+1} (the transmittance behind
+// the hit being processed), the colour S_{k+1} seen behind it (background
+// first), the hits done so far, and where the forward's T fell below the normal
+// floats: the T just before that hit (Tz) and how many composited hits followed
+// it (mz, -1 when T stayed normal). Behind that hit T is taken as 0 (it is below
+// 1.2e-38 there).
+struct Back {
+    float T, Sr, Sg, Sb, Tz;
+    int32_t done, mz;
+};
+
+__device__ inline Back back_init(const float4 fin, const uint4 last, float bgr, float bgg, float bgb)
+{
+    Back B;
+    B.T = fin.w;
+    B.Sr = bgr;
+    B.Sg = bgg;
+    B.Sb = bgb;
+    B.Tz = __uint_as_float(last.z);
+    B.mz = int32_t(last.w);
+    B.done = 0;
+    return B;
+}
+
+// T_k of the next hit (back to front) with opacity al: T_{k+1} / (1 - al), except
+// 0 behind the hit that took T below the normal floats and the saved T at that hit
+// (a select, so a quotient 0/0 there is never used).
+__device__ inline float back_T(const Back &B, float al)
+{
+    const float Td = B.T * __builtin_amdgcn_rcpf(1.0f - al);
+    return B.done < B.mz ? 0.0f : (B.done == B.mz ? B.Tz : Td);
+}
+
+// hit k (alpha al, colour c) now lies behind the next hit: S <- al c + (1 - al) S
+__device__ inline void back_over(Back &B, float al, float cr, float cg, float cb)
+{
+    B.Sr = __builtin_fmaf(al, cr - B.Sr, B.Sr);
+    B.Sg = __builtin_fmaf(al, cg - B.Sg, B.Sg);
+    B.Sb = __builtin_fmaf(al, cb - B.Sb, B.Sb);
+}
+
+// Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation.
+//   dL/dalpha_k = T_k <g, c_k - S_{k+1}>,  dL/dc_k = alpha_k T_k g,
+// then alpha's chain rule (grad_hit). The active lanes' contributions are summed
+// per distinct Gaussian through LDS and one 14-lane segment of an atomic
+// instruction adds each Gaussian's totals to its 64-byte accumulator line (four
+// Gaussians per instruction).
 template <bool COUNT>
-__device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, uint32_t gid, const Ray &ray,
-                                   const HitData &H, const Accum &A, const LaneGrad &Gd, float bgr, float bgg,
-                                   float bgb, bool zc, const float *__restrict__ quat, float *gacc, int lane,
-                                   uint64_t &c_group)
+__device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, const Ray &ray, const HitData &H,
+                                   float Tk, const Back &B, const LaneGrad &Gd, bool zc, const float *__restrict__ quat,
+                                   float *gacc, int lane, uint64_t &c_group)
 {
     GradOut G;
 #pragma unroll
     for (int v = 0; v < 14; ++v) G.v[v] = 0.0f;
     if (act) {
-        float dLda;
-        if (stopped) {
-            dLda = H.Tk * (Gd.gr * (H.cr - bgr) + Gd.gg * (H.cg - bgg) + Gd.gb * (H.cb - bgb));
-        } else {
-            const float rem = Gd.gr * (Gd.Cor - A.Cr) + Gd.gg * (Gd.Cog - A.Cg) + Gd.gb * (Gd.Cob - A.Cb);
-            dLda = H.Tk * (Gd.gr * H.cr + Gd.gg * H.cg + Gd.gb * H.cb) - rem / (1.0f - H.al);
-        }
+        const float dLda = Tk * (Gd.gr * (H.cr - B.Sr) + Gd.gg * (H.cg - B.Sg) + Gd.gb * (H.cb - B.Sb));
         grad_hit(ray, H.r0, H.r1, H.r2, H.g, H.h2, quat, gid, dLda, H.al, G);
-        const float wgt = H.al * H.Tk;
+        const float wgt = H.al * Tk;
         G.v[11] = zc ? 0.0f : Gd.gr * wgt;
         G.v[12] = zc ? 0.0f : Gd.gg * wgt;
         G.v[13] = zc ? 0.0f : Gd.gb * wgt;
@@ -475,6 +532,47 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, bool stopped, ui
     }
 }
 
+// ------------------------------------------------------------ stored lists
+
+// Row cursor of a packet's stored list (wave-uniform).
+struct ListCursor {
+    int32_t rows;   // rows stored
+    int32_t chunk;  // current chunk (-1: none yet)
+    bool ok;        // false once the pool was found exhausted
+};
+
+// Appends one row (one value per lane; called from wave-uniform control flow): a
+// new chunk, linked to the packet's previous one, is taken from the pool every
+// kListRows rows. Once the pool is exhausted the packet stores nothing more (the
+// adjoint then traverses for its rays, or, for the paper variant, the sticky
+// status reports it).
+__device__ inline void list_append(const ListPool &pool, ListCursor &L, uint32_t entry, int lane, int32_t &stored,
+                                   bool paper, int32_t *status)
+{
+    if (!L.ok) return;
+    if ((L.rows & (kListRows - 1)) == 0) {
+        int32_t c = 0;
+        if (lane == 0) {
+            const unsigned long long k = atomicAdd(pool.hdr, 1ull);
+            c = k < (unsigned long long)pool.chunks ? int32_t(k) : -1;
+        }
+        c = __builtin_amdgcn_readfirstlane(c);
+        if (c < 0) {
+            L.ok = false;
+            if (lane == 0) {
+                atomicOr(pool.hdr + 1, 1ull);
+                if (paper) atomicOr(status, kStatusListPool);
+            }
+            return;
+        }
+        if (lane == 0) pool.prev[c] = L.chunk;
+        L.chunk = c;
+    }
+    pool.slots[(int64_t(L.chunk) * kListRows + (L.rows & (kListRows - 1))) * kWave + lane] = entry;
+    if (entry < kListSecond) ++stored;
+    ++L.rows;
+}
+
 // min of two floats that are never NaN-signalling, as the bare instruction
 __device__ inline float fmin_bare(float a, float b)
 {
@@ -488,11 +586,11 @@ constexpr int32_t kDone = INT32_MIN;
 // Wave-uniform descent from `node` through internal nodes to the next leaf
 // (returned as ~leaf) or to the end of the walk (kDone). A child is entered
 // when some live lane's ray overlaps its box within [t_lo, t_hi]; when both
-// are, the one the leader lane reaches first is taken and the other pushed
-// (stack entry k lives in lane k of `stackv`). Ordering by the leader lane
-// costs one compare instead of a vote and, in simulation at the scene-scale
+// are, the one the leader lane reaches first (REV: leaves last) is taken and the
+// other pushed (stack entry k lives in lane k of `stackv`). Ordering by the leader
+// lane costs one compare instead of a vote and, in simulation at the scene-scale
 // workload, visits within 0.5 % as many nodes as a majority vote.
-template <int OCT, bool COUNT>
+template <int OCT, bool COUNT, bool REV>
 __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes, const Slab &sl, uint64_t lead_bit,
                                   float t_lo, float t_hi_w, int lane, int32_t stack_depth, int32_t &sp,
                                   int32_t &stackv, bool &overflow, uint64_t &c_node, uint64_t &c_lchild)
@@ -517,8 +615,9 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
             c_lchild += __popcll(bl) + __popcll(br);
         }
         if (bl != 0 && br != 0) {
-            // both entered: the child the leader lane (lowest live lane) reaches first goes first
-            const bool lfirst = (wave_ballot(ln <= rn) & lead_bit) != 0;
+            // both entered: the child the leader lane (lowest live lane) reaches first (REV: leaves
+            // last) goes first
+            const bool lfirst = (wave_ballot(REV ? lf >= rf : ln <= rn) & lead_bit) != 0;
             if (sp >= stack_depth) {
                 overflow = true;
                 return kDone;
@@ -540,9 +639,39 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 
 #define RS_DESCEND_CASE(O)                                                                                    \
     case O:                                                                                                   \
-        node = descend<O, COUNT>(node, nodes, sl, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,             \
-                                 stackv, overflow, c_node, c_lchild);                                         \
+        node = descend<O, COUNT, kRev>(node, nodes, sl, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,       \
+                                       stackv, overflow, c_node, c_lchild);                                   \
         break;
+
+// The wave-uniform walk of the whole BVH for one round: descend to a leaf, test it
+// (leaf(j), which may move t_lo / t_hi_w), resume from the stack.
+#define RS_WALK_BVH()                                                                                         \
+    {                                                                                                         \
+        int32_t node = P.root;                                                                                \
+        int32_t sp = 0;                                                                                       \
+        int32_t stackv = 0;                                                                                   \
+        const uint64_t live_mask = wave_ballot(live);                                                         \
+        const uint64_t lead_bit = live_mask & (~live_mask + 1);                                               \
+        for (;;) {                                                                                            \
+            switch (oct) {                                                                                    \
+                RS_DESCEND_CASE(0)                                                                            \
+                RS_DESCEND_CASE(1)                                                                            \
+                RS_DESCEND_CASE(2)                                                                            \
+                RS_DESCEND_CASE(3)                                                                            \
+                RS_DESCEND_CASE(4)                                                                            \
+                RS_DESCEND_CASE(5)                                                                            \
+                RS_DESCEND_CASE(6)                                                                            \
+                RS_DESCEND_CASE(7)                                                                            \
+            default:                                                                                          \
+                RS_DESCEND_CASE(kMixedOctant)                                                                 \
+            }                                                                                                 \
+            if (node == kDone) break;                                                                         \
+            leaf(~node);                                                                                      \
+            if (sp == 0) break;                                                                               \
+            --sp;                                                                                             \
+            node = __builtin_amdgcn_readlane(stackv, sp);                                                     \
+        }                                                                                                     \
+    }
 
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
 // (512 / waves): the adjoint carries the gradient temporaries as well. The
@@ -582,18 +711,21 @@ constexpr int waves_for(int K, bool bwd)
                : (K <= 8 ? 6 : (K <= 16 ? RS_FWD16_WAVES : (K <= 24 ? RS_FWD24_WAVES : (K <= 32 ? RS_FWD32_WAVES : RS_FWD48_WAVES))));
 }
 
-template <int K, bool BWD, bool BRUTE, bool COUNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K, BWD)))) void k_render(
+// ------------------------------------------------------------ forward render
+
+template <int K, bool BRUTE, bool COUNT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K, false)))) void k_render(
     const float4 *__restrict__ records, const float4 *__restrict__ nodes, const int32_t *__restrict__ gidx,
     const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
 {
+    constexpr bool kRev = false;
     const int lane = threadIdx.x;
     int64_t iter_pkt = 0;
     const int xcd = xcd_id();
     int qi = 0;
     // work counters (wave-uniform, scalar registers; only in the COUNT variants)
     uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
-             c_group = 0;
+             c_rows = 0;
     for (;;) {
         const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
@@ -611,46 +743,21 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 
         Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
         bool live = valid && P.n_gauss > 0 && tmax > P.t_min;
-        double last = -kNoHit;  // keys of this round must exceed it
-        LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        double last = -kNoHit;  // the last consumed key; keys of the next round must exceed it
+        // T just before the composited hit that took T below the normal floats (to 0, or into the
+        // subnormals, where T_{k+1} / (1 - alpha_k) would lose its digits), and that hit's index
+        float Tz = 0.0f;
+        int32_t z = -1;
+        // stored hit lists: the packet's row cursor; per lane the composited ids stored
+        const bool lists = P.lists && S.list != nullptr;
+        ListCursor LC{0, -1, true};
+        int32_t stored = 0;
         // RS_PAPER_GRADIENT forward: after an eps1 stop the lane keeps consuming hits without
         // compositing them, recording their ids while T2 (their transmittance) stays >= eps2
-        const bool paper = !BWD && P.paper && S.ids;
+        const bool paper = P.paper && lists;
         bool phase2 = false;
         float T2 = 1.0f;
         int32_t extra = 0;
-        if (BWD && valid) {
-            Gd.gr = S.grad[3 * ray_id];
-            Gd.gg = S.grad[3 * ray_id + 1];
-            Gd.gb = S.grad[3 * ray_id + 2];
-            const float4 s = S.state[ray_id];
-            Gd.Cor = s.x;
-            Gd.Cog = s.y;
-            Gd.Cob = s.z;
-            if (Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f) live = false;
-            // with stored hit lists the list kernel takes every ray whose list is complete
-            if (S.count && S.count[ray_id] <= P.hit_cap) live = false;
-        }
-        if (BWD && S.count && P.hit_cap > 0) {
-            // A ray whose list overflowed replays its hit_cap stored hits first (the list kernel's
-            // steps, same arithmetic), then traverses only for the hits after the last of them:
-            // its key (t1 recomputed bit for bit, Gaussian index) starts the rounds below. None
-            // of these rays stops within its stored hits, since it composited more.
-            for (int32_t k = 0; k < P.hit_cap; ++k) {
-                const bool act = live;
-                const uint64_t act_mask = wave_ballot(act);
-                if (act_mask == 0) break;
-                if (COUNT) c_lcomp += __popcll(act_mask);
-                const uint32_t gid = act ? uint32_t(S.ids[int64_t(k) * P.n_rays + ray_id]) : 0u;
-                HitData H;
-                composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
-                const bool stopped = act && stop_after(A, P);
-                adjoint_hit<COUNT>(act, act_mask, stopped, gid, ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
-                                   lane, c_group);
-                if (act) last = hit_key(H.t1, gid);
-                if (stopped) live = false;
-            }
-        }
         bool overflow = false;
 
         while (wave_ballot(live)) {
@@ -694,30 +801,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 // While-while traversal: descend internal nodes until a leaf is reached (or the
                 // stack runs dry), then test that leaf; the hit buffer changes only in the leaf step.
                 // The descent is specialised on the wave's direction octant.
-                int32_t node = P.root;
-                int32_t sp = 0;
-                int32_t stackv = 0;
-                const uint64_t live_mask = wave_ballot(live);
-                const uint64_t lead_bit = live_mask & (~live_mask + 1);
-                for (;;) {
-                    switch (oct) {
-                        RS_DESCEND_CASE(0)
-                        RS_DESCEND_CASE(1)
-                        RS_DESCEND_CASE(2)
-                        RS_DESCEND_CASE(3)
-                        RS_DESCEND_CASE(4)
-                        RS_DESCEND_CASE(5)
-                        RS_DESCEND_CASE(6)
-                        RS_DESCEND_CASE(7)
-                    default:
-                        RS_DESCEND_CASE(kMixedOctant)
-                    }
-                    if (node == kDone) break;
-                    leaf(~node);
-                    if (sp == 0) break;
-                    --sp;
-                    node = __builtin_amdgcn_readlane(stackv, sp);
-                }
+                RS_WALK_BVH()
             }
             if (overflow) {
                 if (lane == 0) atomicOr(ptr.status, kStatusStack);
@@ -738,50 +822,63 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 if (!more) break;
                 if (COUNT) c_lcomp += __popcll(act_mask);
                 const uint32_t gid = hit_key_gid(key_s);
-                HitData H;
+                uint32_t entry = kListIdle;
                 if (paper && phase2) {
                     if (act) {
-                        const int32_t slot = A.n + extra;
-                        if (T2 < P.eps2 || slot >= P.max_hits) {
+                        if (T2 < P.eps2 || A.n + extra >= P.max_hits) {
                             live = false;  // the second phase ends before this hit
                         } else {
                             float4 r0, r1, r2, r3;
                             float t1, h2;
                             HitGeom hg;
                             const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3, t1, h2, hg);
-                            S.ids[int64_t(slot) * P.n_rays + ray_id] = int32_t(gid);
+                            entry = gid | kListSecond;
                             T2 *= 1.0f - al;
                             ++extra;
+                            last = key_s;
                         }
                     }
-                    continue;
+                } else {
+                    HitData H;
+                    composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
+                    if (act) {
+                        entry = gid;
+                        last = key_s;
+                        if (A.T < kMinNormal && H.Tk >= kMinNormal) {
+                            Tz = H.Tk;
+                            z = A.n - 1;
+                        }
+                    }
+                    const bool stopped = act && stop_after(A, P);
+                    if (stopped) {
+                        if (paper && A.T < P.eps1)
+                            phase2 = true;  // stays live for the second phase
+                        else
+                            live = false;
+                    }
                 }
-                composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
-                if (!BWD && act && S.ids && A.n <= P.hit_cap)
-                    S.ids[int64_t(A.n - 1) * P.n_rays + ray_id] = int32_t(gid);
-                const bool stopped = act && stop_after(A, P);
-                if (paper && stopped && A.T < P.eps1) {
-                    phase2 = true;  // stays live for the second phase
-                    continue;
+                if (lists) {
+                    if (COUNT) ++c_rows;
+                    list_append(ptr.pool, LC, entry, lane, stored, paper, ptr.status);
                 }
-                if (BWD)
-                    adjoint_hit<COUNT>(act, act_mask, stopped, gid, ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
-                                       lane, c_group);
-                if (stopped) live = false;
             }
             // a lane whose buffer did not fill has consumed all its hits
             if (live && round_last == kNoHit) live = false;
-            last = round_last;
         }
 
-        if (!BWD && valid) {
-            S.out_rgb[3 * ray_id] = __builtin_fmaf(A.T, bgr, A.Cr);
-            S.out_rgb[3 * ray_id + 1] = __builtin_fmaf(A.T, bgg, A.Cg);
-            S.out_rgb[3 * ray_id + 2] = __builtin_fmaf(A.T, bgb, A.Cb);
-            if (S.state) S.state[ray_id] = make_float4(__builtin_fmaf(A.T, bgr, A.Cr),
-                                                           __builtin_fmaf(A.T, bgg, A.Cg),
-                                                           __builtin_fmaf(A.T, bgb, A.Cb), A.T);
-            if (S.count) S.count[ray_id] = A.n | (extra << 16);
+        if (valid) {
+            const float orr = __builtin_fmaf(A.T, bgr, A.Cr), og = __builtin_fmaf(A.T, bgg, A.Cg),
+                        ob = __builtin_fmaf(A.T, bgb, A.Cb);
+            S.out_rgb[3 * ray_id] = orr;
+            S.out_rgb[3 * ray_id + 1] = og;
+            S.out_rgb[3 * ray_id + 2] = ob;
+            if (S.fin) {
+                S.fin[ray_id] = make_float4(orr, og, ob, A.T);
+                const uint64_t kb = A.n > 0 ? uint64_t(__double_as_longlong(last)) : 0ull;
+                S.last[ray_id] = make_uint4(uint32_t(kb), uint32_t(kb >> 32), __float_as_uint(Tz),
+                                            z >= 0 ? uint32_t(A.n - 1 - z) : 0xffffffffu);
+            }
+            if (lists) S.list[ray_id] = make_int4(A.n, stored, LC.chunk, LC.rows);
         }
     }
     if (COUNT && lane == 0 && c_pkt > 0) {
@@ -793,29 +890,173 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         atomicAdd(ptr.counters + 5, (unsigned long long)c_lbuf);
         atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
         atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
-        atomicAdd(ptr.counters + 8, (unsigned long long)c_group);
+        atomicAdd(ptr.counters + 12, (unsigned long long)c_rows);
     }
 }
 
-// Adjoint from stored hit lists: the forward recorded, per ray, the ids of
-// the Gaussians it composited in order; the adjoint replays that list (no
-// traversal, no hit buffer) with the forward's own per-hit arithmetic. Rays
-// whose list overflowed the capacity are left to the traversal adjoint.
-// Six waves per SIMD (80 VGPRs, a few bytes of spills) hide the gathers better
-// than five; seven and eight spill 56 and 88 bytes per lane and lose 5 and 30 %.
+// ------------------------------------------------- adjoint by re-traversal
+
+// The adjoint re-traverses each ray back to front: a round collects the K largest
+// keys below the previous round's smallest (the first round: up to and including the
+// last composited key the forward saved), keeping them in the hit buffer as negated
+// keys so the same min/max network serves; nodes are culled against [K-th largest t,
+// upper t] and the leader lane takes the child it leaves last first. The round's hits
+// are then processed largest key first. Next to stored lists it serves the rays whose
+// list is incomplete (the pool ran out).
+template <int K, bool BRUTE, bool COUNT>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K, true)))) void k_adjoint_trav(
+    const float4 *__restrict__ records, const float4 *__restrict__ nodes, const int32_t *__restrict__ gidx,
+    const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
+{
+    constexpr bool kRev = true;
+    if (P.overflow_only && ptr.pool.hdr[1] == 0ull) return;  // every list is complete
+    const int lane = threadIdx.x;
+    int64_t iter_pkt = 0;
+    const int xcd = xcd_id();
+    int qi = 0;
+    uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
+             c_group = 0;
+    for (;;) {
+        const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
+        if (pkt >= P.n_packets) break;
+        if (COUNT) ++c_pkt;
+
+        const LaneRay LR = lane_ray(P, ptr, pkt, lane);
+        const RaySet &S = ptr.set[LR.si];
+        const bool zc = S.zero_colour != 0;
+        const bool valid = LR.valid;
+        const int64_t ray_id = LR.id;
+        const Ray ray = LR.ray;
+        const float tmax = LR.tmax;
+        const Slab sl = make_slab(ray);
+        const int oct = wave_octant(sl, valid);
+
+        LaneGrad Gd{0.0f, 0.0f, 0.0f};
+        Back B{1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, -1};
+        bool live = false;
+        double hi = 0.0;  // keys of a round lie below it
+        if (valid) {
+            Gd.gr = S.grad[3 * ray_id];
+            Gd.gg = S.grad[3 * ray_id + 1];
+            Gd.gb = S.grad[3 * ray_id + 2];
+            const uint4 ls = S.last[ray_id];
+            B = back_init(S.fin[ray_id], ls, LR.bgr, LR.bgg, LR.bgb);
+            live = ls.y != 0u && P.n_gauss > 0 && !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
+            if (P.overflow_only) {
+                const int4 li = S.list[ray_id];
+                live = live && li.y < li.x;
+            }
+            // the successor of the last composited key (next Gaussian index, same t)
+            hi = __longlong_as_double((long long)(((uint64_t(ls.y) << 32) | ls.x) + 1ull));
+        }
+        bool overflow = false;
+
+        while (wave_ballot(live)) {
+            HitBuf<K> hb;  // negated keys, ascending: the largest key first
+            hb.clear();
+            if (COUNT) ++c_round;
+            float t_lo = !live ? __builtin_nanf("") : P.t_min;  // rises to the K-th largest t
+            const float t_hi_w = widen(hit_key_t(hi), sl.pad);
+
+            auto leaf = [&](int64_t j) {
+                const int64_t js = __builtin_amdgcn_readfirstlane(int32_t(j));
+                const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
+                             r3 = records[4 * js + 3];
+                const uint32_t gid = uint32_t(gidx[js]);
+                float t1 = 0.0f, h2 = 0.0f;
+                HitGeom hg;
+                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2, hg);
+                const double k = hit_key(t1, gid);
+                const bool cand = live && hit && t1 >= P.t_min && t1 < tmax && k < hi && -k < hb.key[K - 1];
+                const uint64_t cmask = wave_ballot(cand);
+                if (COUNT) {
+                    ++c_leaf;
+                    c_lleaf += __popcll(wave_ballot(live));
+                    c_lbuf += __popcll(cmask);
+                }
+                if (cmask) {
+                    hb.insert(cand ? -k : kNoHit);
+                    if (hb.key[K - 1] != kNoHit) t_lo = fmaxf(P.t_min, hit_key_t(-hb.key[K - 1]));
+                }
+            };
+
+            if (BRUTE) {
+                for (int64_t j = 0; j < P.n_gauss; ++j) leaf(j);
+            } else {
+                RS_WALK_BVH()
+            }
+            if (overflow) {
+                if (lane == 0) atomicOr(ptr.status, kStatusStack);
+                live = false;
+                break;
+            }
+
+            const double round_first = hb.key[K - 1];  // minus the round's smallest key (kNoHit: not full)
+            bool more = true;
+            for (int s = 0; s < K; ++s) {
+                const double nk = hb.key[0];
+                hb.pop_front();
+                const bool act = more && live && nk != kNoHit;
+                const uint64_t act_mask = wave_ballot(act);
+                more = act_mask != 0;
+                if (!more) break;
+                if (COUNT) c_lcomp += __popcll(act_mask);
+                const uint32_t gid = hit_key_gid(nk);
+                HitData H;
+                recompute_hit(act, gid, ray, records, inv, ptr.rgb, zc, P.Q, H);
+                const float Tk = back_T(B, H.al);
+                adjoint_hit<COUNT>(act, act_mask, gid, ray, H, Tk, B, Gd, zc, ptr.quat, ptr.gacc, lane, c_group);
+                if (act) {
+                    back_over(B, H.al, H.cr, H.cg, H.cb);
+                    B.T = Tk;
+                    ++B.done;
+                }
+            }
+            // a lane whose buffer did not fill has reached its first hit
+            if (live) {
+                if (round_first == kNoHit)
+                    live = false;
+                else
+                    hi = -round_first;
+            }
+        }
+    }
+    if (COUNT && lane == 0 && c_pkt > 0) {
+        atomicAdd(ptr.counters + 1, (unsigned long long)c_node);
+        atomicAdd(ptr.counters + 2, (unsigned long long)c_leaf);
+        atomicAdd(ptr.counters + 3, (unsigned long long)c_round);
+        atomicAdd(ptr.counters + 4, (unsigned long long)c_lleaf);
+        atomicAdd(ptr.counters + 5, (unsigned long long)c_lbuf);
+        atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
+        atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
+        atomicAdd(ptr.counters + 8, (unsigned long long)c_group);
+        atomicAdd(ptr.counters + 13, (unsigned long long)c_pkt);
+    }
+}
+
+// ------------------------------------------------- adjoint from stored lists
+
+// The forward appended one row per compositing step of each packet; the adjoint
+// walks the packet's rows from the last to the first, so every lane meets its
+// own hits back to front (rows where it was idle hold kListIdle), and recomputes
+// each hit with the forward's own per-hit arithmetic: no traversal and no hit
+// buffer. The paper variant's second-phase hits (flagged, after the composited
+// ones) only build the colour behind the last composited hit. Rays whose list is
+// incomplete are left to the traversal adjoint.
+// Six waves per SIMD hide the gathers better than five; seven and eight spill.
 #ifndef RS_LIST_WAVES
 #define RS_LIST_WAVES 6
 #endif
 template <bool COUNT>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVES))) void k_adjoint_list(const float4 *__restrict__ records,
-                                                     const int32_t *__restrict__ inv, const Ptrs ptr,
-                                                     const RenderParams P)
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVES))) void k_adjoint_list(
+    const float4 *__restrict__ records, const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
 {
     const int lane = threadIdx.x;
     int64_t iter_pkt = 0;
     const int xcd = xcd_id();
     int qi = 0;
     uint64_t c_pkt = 0, c_lcomp = 0, c_group = 0;
+    const ListPool pool = ptr.pool;
     for (;;) {
         const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
@@ -823,72 +1064,42 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
         const LaneRay LR = lane_ray(P, ptr, pkt, lane);
         const RaySet &S = ptr.set[LR.si];
         const bool zc = S.zero_colour != 0;
-        int32_t cnt = 0, extra = 0;
-        float Tfin = 1.0f;
-        LaneGrad Gd{0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+        LaneGrad Gd{0.0f, 0.0f, 0.0f};
+        Back B{1.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0, -1};
+        int4 li = make_int4(0, 0, -1, 0);
+        bool live = false;
         if (LR.valid) {
-            // the paper variant packs its second-phase length above 16 bits (both are at most
-            // hit_list <= 4096 there); otherwise the count is stored as is (unbounded K_max)
-            const int32_t packed = S.count[LR.id];
-            cnt = P.paper ? packed & 0xffff : packed;
-            extra = P.paper ? packed >> 16 : 0;
+            li = S.list[LR.id];
             Gd.gr = S.grad[3 * LR.id];
             Gd.gg = S.grad[3 * LR.id + 1];
             Gd.gb = S.grad[3 * LR.id + 2];
-            const float4 st = S.state[LR.id];
-            Gd.Cor = st.x;
-            Gd.Cog = st.y;
-            Gd.Cob = st.z;
-            Tfin = st.w;
+            B = back_init(S.fin[LR.id], S.last[LR.id], LR.bgr, LR.bgg, LR.bgb);
+            live = li.x > 0 && li.y == li.x && P.n_gauss > 0 && !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
         }
-        const bool live = LR.valid && cnt > 0 && cnt <= P.hit_cap && P.n_gauss > 0 &&
-                          !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
-        // RS_PAPER_GRADIENT: the colour R2 behind the last composited hit is that of the
-        // second-phase hits (then the background) instead of the background alone; the
-        // final colour the adjoint differentiates becomes C_<=L + T_{L+1} R2
-        float bgr = LR.bgr, bgg = LR.bgg, bgb = LR.bgb;
-        if (P.paper) {
-            float R2r = 0.0f, R2g = 0.0f, R2b = 0.0f, T2 = 1.0f;
-            for (int32_t k = 0;; ++k) {
-                const bool a2 = live && k < extra;
-                if (!wave_ballot(a2)) break;
-                if (a2) {
-                    const uint32_t gid = uint32_t(S.ids[int64_t(cnt + k) * P.n_rays + LR.id]);
-                    float4 r0, r1, r2, r3;
-                    float t1, h2;
-                    HitGeom hg;
-                    const float al = hit_alpha(gid, LR.ray, records, inv, P.Q, r0, r1, r2, r3, t1, h2, hg);
-                    if (!zc) {
-                        const float w = T2 * al;
-                        R2r = __builtin_fmaf(w, ptr.rgb[3 * gid], R2r);
-                        R2g = __builtin_fmaf(w, ptr.rgb[3 * gid + 1], R2g);
-                        R2b = __builtin_fmaf(w, ptr.rgb[3 * gid + 2], R2b);
-                    }
-                    T2 *= 1.0f - al;
-                }
-            }
-            R2r = __builtin_fmaf(T2, bgr, R2r);
-            R2g = __builtin_fmaf(T2, bgg, R2g);
-            R2b = __builtin_fmaf(T2, bgb, R2b);
-            Gd.Cor += Tfin * (R2r - bgr);
-            Gd.Cog += Tfin * (R2g - bgg);
-            Gd.Cob += Tfin * (R2b - bgb);
-            bgr = R2r;
-            bgg = R2g;
-            bgb = R2b;
-        }
-        Accum A{1.0f, 0.0f, 0.0f, 0.0f, 0};
-        for (int32_t k = 0;; ++k) {
-            const bool act = live && k < cnt;
-            const uint64_t act_mask = wave_ballot(act);
-            if (!act_mask) break;
-            if (COUNT) c_lcomp += __popcll(act_mask);
-            const uint32_t gid = act ? uint32_t(S.ids[int64_t(k) * P.n_rays + LR.id]) : 0u;
+        // the packet's rows (lane 0 always holds one of the packet's rays)
+        const int32_t rows = __builtin_amdgcn_readfirstlane(li.w);
+        int32_t chunk = __builtin_amdgcn_readfirstlane(li.z);
+        if (!wave_ballot(live)) continue;
+        for (int32_t row = rows - 1; row >= 0; --row) {
+            if ((row & (kListRows - 1)) == kListRows - 1 && row != rows - 1) chunk = pool.prev[chunk];
+            const uint32_t e =
+                live ? pool.slots[(int64_t(chunk) * kListRows + (row & (kListRows - 1))) * kWave + lane] : kListIdle;
+            const bool act = e != kListIdle;
+            if (!wave_ballot(act)) continue;
+            const bool comp = act && e < kListSecond;
+            const uint32_t gid = e & ~kListSecond;
             HitData H;
-            composite_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P, A, H);
-            const bool stopped = act && stop_after(A, P);
-            adjoint_hit<COUNT>(act, act_mask, stopped, gid, LR.ray, H, A, Gd, bgr, bgg, bgb, zc, ptr.quat, ptr.gacc,
-                               lane, c_group);
+            recompute_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P.Q, H);
+            const float Tk = back_T(B, H.al);
+            const uint64_t comp_mask = wave_ballot(comp);
+            if (COUNT) c_lcomp += __popcll(comp_mask);
+            if (comp_mask)
+                adjoint_hit<COUNT>(comp, comp_mask, gid, LR.ray, H, Tk, B, Gd, zc, ptr.quat, ptr.gacc, lane, c_group);
+            if (act) back_over(B, H.al, H.cr, H.cg, H.cb);
+            if (comp) {
+                B.T = Tk;
+                ++B.done;
+            }
         }
     }
     if (COUNT && lane == 0 && c_pkt > 0) {
@@ -939,6 +1150,16 @@ __global__ void k_zero_queue(uint32_t *q)
     if (threadIdx.x < kXcdQueues) q[threadIdx.x] = 0u;
 }
 
+__global__ void k_zero_pool_header(unsigned long long *h)
+{
+    if (threadIdx.x < 2) h[threadIdx.x] = 0ull;
+}
+
+void reset_pool(const ListPool &pool, hipStream_t st)
+{
+    if (pool.hdr) k_zero_pool_header<<<1, 64, 0, st>>>(pool.hdr);
+}
+
 static void zero(float *p, int64_t n, hipStream_t st)
 {
     if (!p || n <= 0) return;
@@ -947,26 +1168,30 @@ static void zero(float *p, int64_t n, hipStream_t st)
     k_zero_f32<<<int(blocks), 256, 0, st>>>(p, n);
 }
 
-template <int K, bool BWD>
-static void launch_kb(int grid, const float4 *records, const float4 *nodes, const int32_t *gidx, const int32_t *inv,
-                      const Ptrs &ptr, const RenderParams &P, hipStream_t st)
-{
-    if (P.brute)
-        k_render<K, BWD, true, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-    else if (P.count)
-        k_render<K, BWD, false, true><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-    else
-        k_render<K, BWD, false, false><<<grid, kWave, 0, st>>>(records, nodes, gidx, inv, ptr, P);
-}
+struct KernArgs {
+    int grid;
+    const float4 *records, *nodes;
+    const int32_t *gidx, *inv;
+};
 
 template <int K>
-static void launch_k(bool bwd, int grid, const float4 *records, const float4 *nodes, const int32_t *gidx,
-                     const int32_t *inv, const Ptrs &ptr, const RenderParams &P, hipStream_t st)
+static void launch_k(Pass pass, const KernArgs &a, const Ptrs &ptr, const RenderParams &P, hipStream_t st)
 {
-    if (bwd)
-        launch_kb<K, true>(grid, records, nodes, gidx, inv, ptr, P, st);
-    else
-        launch_kb<K, false>(grid, records, nodes, gidx, inv, ptr, P, st);
+    if (pass == Pass::Forward) {
+        if (P.brute)
+            k_render<K, true, false><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+        else if (P.count)
+            k_render<K, false, true><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+        else
+            k_render<K, false, false><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+    } else {
+        if (P.brute)
+            k_adjoint_trav<K, true, false><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+        else if (P.count)
+            k_adjoint_trav<K, false, true><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+        else
+            k_adjoint_trav<K, false, false><<<a.grid, kWave, 0, st>>>(a.records, a.nodes, a.gidx, a.inv, ptr, P);
+    }
 }
 
 void zero_gacc(const BvhDesc &D, hipStream_t st)
@@ -984,9 +1209,9 @@ void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st)
                                                              grads->d_opacity, grads->d_rgb);
 }
 
-// One launch over one or two ray sets sharing a layout (same count, same views).
+// One launch over up to kMaxSets ray sets sharing a layout (same count, same views).
 int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int nsets, const SetDesc *sets,
-                bool bwd, hipStream_t st, bool list_adjoint)
+                const ListPool &pool, Pass pass, hipStream_t st)
 {
     Layout L = make_layout(D.n);
     char *ws = D.ws;
@@ -1010,8 +1235,9 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     P.packets_per_set = packets;
     P.n_packets = packets * nsets;
     P.strip_tiles = kStripTiles;
-    P.hit_cap = sets[0].count ? p->hit_list : 0;
-    P.paper = (p->flags & RS_PAPER_GRADIENT) && sets[0].count ? 1 : 0;
+    P.lists = pool.chunks > 0 ? 1 : 0;
+    P.overflow_only = (pass == Pass::AdjointTraverse && P.lists) ? 1 : 0;
+    P.paper = (p->flags & RS_PAPER_GRADIENT) && P.lists ? 1 : 0;
     P.eps2 = p->eps2;
     P.chunk = (P.n_packets + kXcdQueues - 1) / kXcdQueues;
 
@@ -1027,9 +1253,9 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
         R.bgray = E.rays->bg;
         R.grad = E.grad;
         R.out_rgb = E.out_rgb;
-        R.state = reinterpret_cast<float4 *>(E.state);
-        R.count = E.count;
-        R.ids = E.ids;
+        R.fin = E.state.fin;
+        R.last = E.state.last;
+        R.list = E.state.list;
         for (int c = 0; c < 3; ++c) R.bg[c] = E.bg[c];
         R.zero_colour = E.zero_colour;
     }
@@ -1037,39 +1263,41 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     ptr.queue = h->xq;
     ptr.counters = reinterpret_cast<unsigned long long *>(h->counters);
     ptr.gacc = reinterpret_cast<float *>(ws + L.gacc);
+    ptr.pool = pool;
 
+    if (pass == Pass::Forward && P.lists) reset_pool(pool, st);
     if (P.n_packets > 0) {
-        int grid;
+        KernArgs a;
         if (P.persistent) {
             k_zero_queue<<<1, 64, 0, st>>>(h->xq);
             int dev = 0, cus = 256;
             (void)hipGetDevice(&dev);
             (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
             const int64_t waves = int64_t(cus) * 24;  // up to 6 waves per SIMD (the most any variant fits)
-            grid = int(waves < P.n_packets ? waves : P.n_packets);
+            a.grid = int(waves < P.n_packets ? waves : P.n_packets);
         } else {
             const int64_t deal = int64_t(kXcdQueues) * kXcdRun;
-            grid = int((P.n_packets + deal - 1) / deal * deal);
+            a.grid = int((P.n_packets + deal - 1) / deal * deal);
         }
-        const float4 *records = reinterpret_cast<const float4 *>(ws + L.records);
-        const float4 *nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
-        const int32_t *gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
-        const int32_t *inv = reinterpret_cast<const int32_t *>(ws + L.inv);
+        a.records = reinterpret_cast<const float4 *>(ws + L.records);
+        a.nodes = reinterpret_cast<const float4 *>(ws + L.nodes);
+        a.gidx = reinterpret_cast<const int32_t *>(ws + L.gidx);
+        a.inv = reinterpret_cast<const int32_t *>(ws + L.inv);
         // the hit-buffer size never changes the result (same hits, same order, same arithmetic);
         // the default is the fastest measured size on MI355X
-        if (list_adjoint) {
+        if (pass == Pass::AdjointList) {
             if (P.count)
-                k_adjoint_list<true><<<grid, kWave, 0, st>>>(records, inv, ptr, P);
+                k_adjoint_list<true><<<a.grid, kWave, 0, st>>>(a.records, a.inv, ptr, P);
             else
-                k_adjoint_list<false><<<grid, kWave, 0, st>>>(records, inv, ptr, P);
+                k_adjoint_list<false><<<a.grid, kWave, 0, st>>>(a.records, a.inv, ptr, P);
         } else {
             const int K = p->kbuf > 0 ? p->kbuf : 48;
             switch (K) {
-            case 8: launch_k<8>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-            case 16: launch_k<16>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-            case 24: launch_k<24>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-            case 32: launch_k<32>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
-            case 48: launch_k<48>(bwd, grid, records, nodes, gidx, inv, ptr, P, st); break;
+            case 8: launch_k<8>(pass, a, ptr, P, st); break;
+            case 16: launch_k<16>(pass, a, ptr, P, st); break;
+            case 24: launch_k<24>(pass, a, ptr, P, st); break;
+            case 32: launch_k<32>(pass, a, ptr, P, st); break;
+            case 48: launch_k<48>(pass, a, ptr, P, st); break;
             default: return RS_ERR_INVALID_ARG;
             }
         }
@@ -1084,26 +1312,28 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     SetDesc S{};
     S.rays = rays;
     S.out_rgb = out_rgb;
-    S.state = state;
     S.grad = grad;
     for (int c = 0; c < 3; ++c) S.bg[c] = p->bg[c];
     S.zero_colour = (p->flags & RS_ZERO_COLOUR) ? 1 : 0;
-    if (state && p->hit_list > 0 && rays->n > 0) {
-        const StateLayout sl = state_layout(rays->n, p->hit_list);
-        S.count = reinterpret_cast<int32_t *>(static_cast<char *>(state) + sl.count);
-        S.ids = reinterpret_cast<int32_t *>(static_cast<char *>(state) + sl.ids);
+    const int32_t cap = p->hit_list;
+    S.state = state_at(state, rays->n, cap);
+    ListPool pool{nullptr, nullptr, nullptr, 0};
+    if (state && cap > 0 && rays->n > 0) {
+        const StateLayout sl = state_layout(rays->n, cap);
+        pool = list_pool_at(static_cast<char *>(state) + sl.pool, sl.chunks);
     }
+    if (!bwd) return launch_sets(D, g, p, 1, &S, pool, Pass::Forward, st);
     int e;
-    if (!bwd) return launch_sets(D, g, p, 1, &S, false, st);
     zero_gacc(D, st);
-    if (S.count) {
-        // stored lists first; the traversal adjoint then takes only the rays whose list
-        // overflowed, which can happen only when K_max exceeds the capacity
-        if ((e = launch_sets(D, g, p, 1, &S, true, st, true))) return e;
-        if (p->max_hits == 0 || p->max_hits > p->hit_list)
-            if ((e = launch_sets(D, g, p, 1, &S, true, st))) return e;
+    if (pool.chunks > 0) {
+        // stored lists first; the traversal adjoint then takes the rays whose list is
+        // incomplete (it exits at once when the forward found the pool large enough).
+        // The paper variant has no traversal form: its pool running out is an error.
+        if ((e = launch_sets(D, g, p, 1, &S, pool, Pass::AdjointList, st))) return e;
+        if (!(p->flags & RS_PAPER_GRADIENT))
+            if ((e = launch_sets(D, g, p, 1, &S, pool, Pass::AdjointTraverse, st))) return e;
     } else {
-        if ((e = launch_sets(D, g, p, 1, &S, true, st))) return e;
+        if ((e = launch_sets(D, g, p, 1, &S, pool, Pass::AdjointTraverse, st))) return e;
     }
     scatter_gacc(D, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;

@@ -28,6 +28,9 @@ class Params:
     tile_width: int = 0
     hit_list: int = 0
     eps2: float = 1e-4
+    # wrapper-side only: the autograd Functions read the sticky device status
+    # after each call (a stream synchronisation) and raise on a device error
+    raise_on_status: bool = False
 
     def c(self):
         p = L.rs_params()
@@ -127,16 +130,27 @@ def state_bytes(n, params=None):
 
 
 def new_state(n, params, device="cuda"):
-    """Ray state for render_fwd / render_bwd: float32 [n, 4] (colour, T) when
-    params.hit_list == 0, else a flat buffer whose first 4 n floats are that."""
-    if not params.hit_list:
-        return torch.empty((n, 4), dtype=torch.float32, device=device)
-    return torch.empty(max(state_bytes(n, params) // 4, 64), dtype=torch.float32, device=device)
+    """Ray state for render_fwd / render_bwd: a flat float32 buffer of
+    rs_ray_state_bytes(n, params) bytes whose first 4 n floats are the final
+    colour and transmittance of each ray (see state_colour)."""
+    return torch.empty(max((state_bytes(n, params) + 3) // 4, 64), dtype=torch.float32, device=device)
 
 
 def state_colour(state, n):
     """The [n, 4] (final colour, final transmittance) part of a ray state."""
-    return state if state.dim() == 2 else state[:4 * n].view(n, 4)
+    return state.reshape(-1)[:4 * n].view(n, 4)
+
+
+def _check_state(state, n, params):
+    """The C ABI takes the ray state without a size: check it here."""
+    if state is None:
+        return None
+    state = _dev(state, "state") if state.dtype == torch.float32 else _dev(state, "state", state.dtype)
+    need = state_bytes(n, params)
+    have = state.numel() * state.element_size()
+    if have < need:
+        raise ValueError(f"ray state holds {have} bytes, rs_ray_state_bytes({n}, params) needs {need}")
+    return state
 
 
 def workspace_bytes(n):
@@ -162,6 +176,7 @@ def render_fwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, out=None, sta
         out = torch.empty((n, 3), dtype=torch.float32, device=rays.origin.device)
     if want_state and state is None:
         state = new_state(n, params, rays.origin.device)
+    state = _check_state(state, n, params)
     gc, rc, pc = g.c(), rays.c(), params.c()
     L.check(lib.rs_render_fwd(C.byref(bvh.desc), C.byref(gc), C.byref(rc), C.byref(pc), _ptr(out), _ptr(state),
                               _stream()), "rs_render_fwd")
@@ -171,8 +186,12 @@ def render_fwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, out=None, sta
 def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, state, grads=None):
     lib = L.lib()
     grad_rgb = _dev(grad_rgb.contiguous(), "grad_rgb")
+    if grad_rgb.numel() != 3 * rays.n:
+        raise ValueError("grad_rgb must hold [n_rays, 3] values")
+    if state is None:
+        raise ValueError("render_bwd needs the ray state of the forward call")
+    state = _check_state(state, rays.n, params)
     if grads is None:
-        dev = g.mean.device
         grads = (torch.empty_like(g.mean), torch.empty_like(g.scale), torch.empty_like(g.quat),
                  torch.empty_like(g.opacity), torch.empty_like(g.rgb))
     gr = L.rs_grads(*[_ptr(t) for t in grads])
@@ -185,7 +204,8 @@ def render_bwd(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb, sta
 def _params_from_c(cp, like):
     return Params(Q=like.Q, eps1=like.eps1, t_min=like.t_min, max_hits=like.max_hits, bg=tuple(like.bg),
                   flags=int(cp.flags), kbuf=int(cp.kbuf), stack_depth=int(cp.stack_depth),
-                  tile_width=int(cp.tile_width), hit_list=int(cp.hit_list), eps2=like.eps2)
+                  tile_width=int(cp.tile_width), hit_list=int(cp.hit_list), eps2=like.eps2,
+                  raise_on_status=like.raise_on_status)
 
 
 def autotune(bvh: BVH, g: Gaussians, rays: Rays, params: Params, grad_rgb=None, reps=2):
@@ -216,15 +236,39 @@ def read_status(bvh: BVH):
     return int(L.lib().rs_read_status(C.byref(bvh.desc), _stream()))
 
 
+def raise_on_status(bvh: BVH, what):
+    """Synchronise and raise if a device-side check failed since the build."""
+    code = read_status(bvh)
+    if code != L.RS_OK:
+        raise L.RaySplatsError(f"{what}: device status {L.lib().rs_status_string(code).decode()} ({code})")
+
+
 COUNTER_NAMES = ("packets", "node_visits", "leaf_visits", "rounds", "lane_leaf_tests", "lane_hits_buffered",
-                 "lane_composited", "lane_child_overlaps", "grad_groups", "r9", "r10", "r11")
+                 "lane_composited", "lane_child_overlaps", "grad_groups", "list_packets", "list_composited",
+                 "list_grad_groups", "list_rows", "adjoint_packets", "c14", "c15")
 
 
 def read_counters(bvh: BVH):
-    out = np.zeros(12, np.uint64)
+    out = np.zeros(16, np.uint64)
     L.check(L.lib().rs_read_counters(C.byref(bvh.desc), out.ctypes.data_as(C.c_void_p), _stream()),
             "rs_read_counters")
     return dict(zip(COUNTER_NAMES, (int(x) for x in out)))
+
+
+def hit_lists(rays: Rays, params: Params, state, cap=None):
+    """Host copies of the stored hit lists of a ray state (rs_hit_lists_download):
+    dict(count, stored, extra, ids[n, cap] with -1 padding)."""
+    n = rays.n
+    cap = int(cap or max(params.max_hits, 1))
+    count = np.zeros(max(n, 1), np.int32)
+    stored = np.zeros(max(n, 1), np.int32)
+    extra = np.zeros(max(n, 1), np.int32)
+    ids = np.zeros((max(n, 1), cap), np.int32)
+    rc, pc = rays.c(), params.c()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    L.check(L.lib().rs_hit_lists_download(C.byref(rc), C.byref(pc), _ptr(state), p(count), p(stored), p(extra),
+                                          p(ids), cap, _stream()), "rs_hit_lists_download")
+    return dict(count=count[:n], stored=stored[:n], extra=extra[:n], ids=ids[:n])
 
 
 def download(bvh: BVH):
@@ -395,6 +439,8 @@ class MeshRender(torch.autograd.Function):
         rays = Rays(origin.contiguous(), direction.contiguous(), views=list(views or []))
         gbvh = build_bvh(g, params)
         out, frame = render_mesh_fwd(gbvh, mbvh, g, mesh, shading, rays, params)
+        if params.raise_on_status:
+            raise_on_status(gbvh, "rs_render_mesh_fwd")
         ctx.saved = (gbvh, mbvh, g, mesh, shading, rays, params, frame)
         return out
 
@@ -402,6 +448,8 @@ class MeshRender(torch.autograd.Function):
     def backward(ctx, grad_out):
         gbvh, mbvh, g, mesh, shading, rays, params, frame = ctx.saved
         dm, ds, dq, do, dc = render_mesh_bwd(gbvh, mbvh, g, mesh, shading, rays, params, grad_out.contiguous(), frame)
+        if params.raise_on_status:
+            raise_on_status(gbvh, "rs_render_mesh_bwd")
         return dm, ds, dq, do, dc, None, None, None, None, None, None, None
 
 
@@ -418,6 +466,8 @@ class RaySplatsRender(torch.autograd.Function):
         rays = Rays(origin.contiguous(), direction.contiguous(), views=list(views or []))
         bvh = build_bvh(g, params)
         out, state = render_fwd(bvh, g, rays, params)
+        if params.raise_on_status:
+            raise_on_status(bvh, "rs_render_fwd")
         ctx.saved = (bvh, g, rays, params, state)
         return out
 
@@ -425,6 +475,8 @@ class RaySplatsRender(torch.autograd.Function):
     def backward(ctx, grad_out):
         bvh, g, rays, params, state = ctx.saved
         dm, ds, dq, do, dc = render_bwd(bvh, g, rays, params, grad_out.contiguous(), state)
+        if params.raise_on_status:
+            raise_on_status(bvh, "rs_render_bwd")
         return dm, ds, dq, do, dc, None, None, None, None
 
 

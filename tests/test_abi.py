@@ -68,14 +68,22 @@ def test_defaults_and_strings(L):
     p = L.rs_params()
     lib.rs_default_params(C.byref(p))
     assert abs(p.Q - 11.3449) < 1e-5 and abs(p.eps1 - 1e-4) < 1e-9 and p.max_hits == 512 and p.flags == 0
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert lib.rs_status_string(code)
-    assert lib.rs_ray_state_bytes(10, None) == 160
+    assert b"unknown" not in lib.rs_status_string(L.RS_ERR_LIST_POOL)
+    # final colour/T, then (256-byte aligned) the adjoint's start: 16 bytes per ray each
+    assert lib.rs_ray_state_bytes(10, None) == 256 + 160
     q = L.rs_params()
     lib.rs_default_params(C.byref(q))
     q.hit_list = 8
-    # colour/T, then 256-byte aligned count[n] and ids[C][n]
-    assert lib.rs_ray_state_bytes(10, C.byref(q)) == 256 + 256 + 8 * 10 * 4
+    # then the list bookkeeping (16 bytes per ray) and the pool: a 256-byte header, the
+    # chunk links and whole chunks of 16 rows x 64 slots x 4 bytes (80 slots -> one chunk)
+    assert lib.rs_ray_state_bytes(10, C.byref(q)) == 512 + 256 + 256 + 256 + 16 * 64 * 4
+    q.hit_list = 100
+    n = 100000
+    chunks = (n * 100 + 1023) // 1024
+    head = (n * 16 + 255) // 256 * 256
+    assert lib.rs_ray_state_bytes(n, C.byref(q)) == 3 * head + 256 + (chunks * 4 + 255) // 256 * 256 + chunks * 4096
     a, b = lib.rs_bvh_workspace_bytes(1000), lib.rs_bvh_workspace_bytes(100000)
     assert 0 < a < b and b % 256 == 0
 
@@ -103,8 +111,8 @@ def test_invalid_arguments_are_rejected(L):
         lib.rs_default_params(C.byref(q))
         setattr(q, field, val)
         assert lib.rs_build_bvh(C.byref(g), C.byref(q), fake, 1 << 30, C.byref(out), None) == L.RS_ERR_INVALID_ARG
-    # the paper's gradient variant needs lists that cannot overflow and eps2 in [0, 1]
-    for hit_list, max_hits, eps2 in ((0, 512, 1e-4), (256, 512, 1e-4), (512, 0, 1e-4), (512, 512, 2.0)):
+    # the paper's gradient variant needs stored lists, a finite K_max and eps2 in [0, 1]
+    for hit_list, max_hits, eps2 in ((0, 512, 1e-4), (512, 0, 1e-4), (512, 512, 2.0), (512, 512, -0.5)):
         q = L.rs_params()
         lib.rs_default_params(C.byref(q))
         q.flags, q.hit_list, q.max_hits, q.eps2 = L.RS_PAPER_GRADIENT, hit_list, max_hits, eps2

@@ -57,11 +57,15 @@ def _scene(which):
         return _chain(600)
     if which == "chain20k":
         return _chain(20_000)  # leaves the finish kernel more clusters than fit in LDS
+    if which == "scene1M":
+        return scenes.scene_config4()  # the scene-scale workload's 1M Gaussians
+    if which == "batch300k":
+        return scenes.scene_config3()
     raise ValueError(which)
 
 
 @pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups", "equal_boxes", "local_edge",
-                                   "chain600", "chain20k"])
+                                   "chain600", "chain20k", "batch300k", "scene1M"])
 def test_leaf_boxes_and_ploc_tree_bit_exact(which):
     print("case ploc", which, flush=True)
     sc = _scene(which)
@@ -77,7 +81,7 @@ def test_leaf_boxes_and_ploc_tree_bit_exact(which):
     np.testing.assert_array_equal(got["boxes"], boxes)
 
 
-@pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups"])
+@pytest.mark.parametrize("which", ["config1", "clusters100k", "ragged", "dups", "scene1M"])
 def test_morton_sort_topology_bit_exact(which):
     """The radix-tree builder (RS_BUILD_LBVH)."""
     print("case lbvh", which, flush=True)

@@ -1,7 +1,19 @@
-"""Adjoint parity: GPU gradients (recomputing re-traversal, wave-aggregated
-atomics) against the FP64 oracle adjoint, which is itself pinned by central
-differences. Pixels whose hit set or stop index is within rounding of a
-decision boundary are masked on both sides."""
+"""Adjoint parity: GPU gradients (back-to-front replay from stored lists or by
+re-traversal, wave-aggregated atomics) against the FP64 oracle adjoint, which
+is itself pinned by central differences.
+
+Every comparison is element by element: for each parameter group and every
+entry, |g_gpu - g_oracle| <= 1e-3 |g_oracle| + 1e-3 max |g_oracle|.
+
+A float32 renderer may legitimately composite a different hit sequence than
+the FP64 oracle where a decision sits within rounding (a near-tangent ray, two
+hits at nearly the same depth, T next to eps1). Such a pixel's gradient is that
+of another valid sequence, so it is left out on both sides. Which pixels are
+left out is decided by comparing the GPU's composited sequence (its stored hit
+list) with the oracle's: every pixel that differs must be one the oracle flags
+as within rounding of a decision, and at most 1 % may differ."""
+
+import dataclasses
 
 import numpy as np
 import pytest
@@ -15,6 +27,7 @@ pytestmark = pytest.mark.gpu
 
 REL = 1e-3
 GROUPS = ("mean", "scale", "quat", "opacity", "rgb")
+MAX_DIFFERING = 0.01  # fraction of pixels whose GPU hit sequence may differ from the oracle's
 
 
 def _g():
@@ -23,30 +36,48 @@ def _g():
     return G, R
 
 
-def _unambiguous(sc, o, d, op):
-    cnt, _ = O.alternatives_batch(sc, o, d, op, max_events=3, cap=2)
-    return cnt == 1
+def _differing_pixels(sc, o, d, p, label, cap=512, t_max=None, bg=None):
+    """Pixels whose GPU composited sequence differs from the oracle's; checks
+    that each of them is within rounding of a decision and that they are few."""
+    G, R = _g()
+    op = G.oracle_params(O, p)
+    ids_g, cnt_g = G.sequences(sc, o, d, p, cap=cap, t_max=t_max, bg=bg)
+    ids_o, L_o = O.render_lists(sc, o, d, op, cap=cap, t_max=t_max, bg=bg)
+    diff = (cnt_g != L_o) | np.any(ids_g != ids_o, axis=1)
+    n = len(diff)
+    if diff.any():
+        amb, _ = O.alternatives_batch(sc, o[diff], d[diff], op, max_events=3, cap=2)
+        assert np.all(amb != 1), f"{label}: {int((amb == 1).sum())} pixels differ with no decision within rounding"
+    print(label, "pixels whose hit sequence differs:", int(diff.sum()), "of", n, flush=True)
+    assert diff.sum() <= max(MAX_DIFFERING * n, 1), (int(diff.sum()), n)
+    return diff
+
+
+def _assert_elementwise(got, ref, label, rel=REL):
+    G, _ = _g()
+    G.assert_elementwise(got, ref, label, rel)
+
+
+def _grads_gpu(R, bvh, g, rays, p, grad, state):
+    gg = R.render_bwd(bvh, g, rays, p, grad if torch.is_tensor(grad) else torch.from_numpy(np.float32(grad)).cuda(),
+                      state)
+    torch.cuda.synchronize()
+    assert R.read_status(bvh) == 0
+    return dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in gg)))
 
 
 def _grad_parity(sc, o, d, grad, p, views=None, label=""):
+    """Element-wise parity of the adjoint for the upstream gradient `grad` over
+    the rays (o, d) rendered with params p (and views)."""
     G, R = _g()
     op = G.oracle_params(O, p)
-    mask = _unambiguous(sc, o, d, op)
-    grad = grad * mask[:, None]
+    diff = _differing_pixels(sc, o, d, p, label)
+    grad = np.float32(grad * (~diff)[:, None])
     out, state, status, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
     assert status == 0
-    gg = R.render_bwd(bvh, g, rays, p, G.dev(np.float32(grad)), state=torch.from_numpy(state).cuda())
-    torch.cuda.synchronize()
-    got = dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in gg)))
-    ref = O.render_bwd(sc, o, d, np.float32(grad).astype(np.float64), op)
-    errs = {}
-    for k in GROUPS:
-        num = np.linalg.norm(got[k] - ref[k])
-        den = np.linalg.norm(ref[k])
-        errs[k] = num / den if den > 0 else num
-    print(label, "masked", int((~mask).sum()), "of", len(mask), {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    for k in GROUPS:
-        assert errs[k] <= REL, (k, errs[k])
+    got = _grads_gpu(R, bvh, g, rays, p, grad, state)
+    ref = O.render_bwd(sc, o, d, grad.astype(np.float64), op)
+    _assert_elementwise(got, ref, label)
     return got, ref
 
 
@@ -57,8 +88,10 @@ def test_tiny_scene_gradients():
     cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 24, 20, fov_y_deg=30)
     o, d = pinhole_rays(cam)
     rng = np.random.default_rng(1)
-    _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), R.Params(bg=(0.1, 0.2, 0.3), max_hits=64),
-                 views=[(0, 24, 20)], label="tiny")
+    for hit_list in (0, 64):
+        _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)),
+                     R.Params(bg=(0.1, 0.2, 0.3), max_hits=64, hit_list=hit_list), views=[(0, 24, 20)],
+                     label=f"tiny lists {hit_list}")
 
 
 @pytest.mark.parametrize("n,hit_list", [(1, 0), (1, 64), (3, 64), (3, 0)])
@@ -77,13 +110,72 @@ def test_one_gaussian_per_packet_gradients(n, hit_list):
     assert np.linalg.norm(ref["mean"]) > 0
 
 
-def test_config1_gradients():
-    print("case config1 grads", flush=True)
+@pytest.mark.parametrize("hit_list", [0, 512])
+def test_config1_gradients(hit_list):
+    print("case config1 grads", hit_list, flush=True)
     G, R = _g()
     w = workload(1)
     o, d, views = G.camera_rays(w["cams"])
     rng = np.random.default_rng(2)
-    _grad_parity(w["scene"], o, d, rng.normal(size=(o.shape[0], 3)), R.Params(), views=views, label="config1")
+    _grad_parity(w["scene"], o, d, rng.normal(size=(o.shape[0], 3)), R.Params(hit_list=hit_list), views=views,
+                 label=f"config1 lists {hit_list}")
+
+
+@pytest.mark.parametrize("hit_list", [0, 96])
+def test_near_opaque_scene_gradients(hit_list):
+    """Every opacity in [0.95, 0.999]: T falls by 20 to 1000 per hit, the regime
+    where a front-to-back form that divides by 1 - alpha loses its digits."""
+    print("case near-opaque grads", hit_list, flush=True)
+    G, R = _g()
+    sc = scenes.random_scene(80, 2000, box=0.9, flat_frac=0.3, scale_lo=0.03, scale_hi=0.15)
+    rng = np.random.default_rng(81)
+    sc.opacity[:] = np.float32(rng.uniform(0.95, 0.999, size=sc.n))
+    cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 48, 40, fov_y_deg=40)
+    o, d = pinhole_rays(cam)
+    for eps1 in (1e-4, 0.0):
+        p = R.Params(hit_list=hit_list, eps1=eps1, max_hits=0 if eps1 == 0.0 else 512)
+        _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), p, views=[(0, 48, 40)],
+                     label=f"near-opaque lists {hit_list} eps1 {eps1}")
+
+
+@pytest.mark.parametrize("hit_list", [0, 64])
+@pytest.mark.parametrize("eps1", [0.0, 1e-4])
+def test_fully_opaque_hit_regression(hit_list, eps1):
+    """Opacity exactly 1 on a ray through the mean: alpha = 1, T becomes 0.
+    With eps1 = 0 and no K_max the ray keeps compositing hits whose T is 0; the
+    gradient of the opaque hit still sees the colour behind it, and the hits in
+    front of it get the T they had (the forward saves T where it reaches 0).
+    Every value stays finite and equals the oracle's."""
+    print("case opacity 1", hit_list, eps1, flush=True)
+    G, R = _g()
+    z = np.float32([-1.0, 0.0, 1.0, 2.0])
+    # anisotropic and rotated, so every parameter group has a gradient (an isotropic
+    # Gaussian's quaternion gradient is exactly zero)
+    q = np.float32([[0.9, 0.2, -0.3, 0.1], [0.7, -0.4, 0.5, 0.2], [0.8, 0.1, 0.1, -0.5], [0.6, 0.3, 0.6, 0.4]])
+    sc = scenes.Scene(np.float32([[0.0, 0.0, zz] for zz in z]),
+                      np.float32([[0.3, 0.22, 0.35], [0.25, 0.4, 0.3], [0.2, 0.3, 0.28], [0.33, 0.26, 0.4]]), q,
+                      np.float32([0.5, 1.0, 0.6, 0.7]),
+                      np.float32([[0.9, 0.1, 0.2], [0.2, 0.8, 0.3], [0.1, 0.2, 0.9], [0.5, 0.5, 0.1]]))
+    # rays through the means (alpha exactly 1 at the opaque one) and slightly off them
+    offs = np.float32([[0.0, 0.0], [1e-5, 0.0], [0.02, -0.01], [0.05, 0.05], [0.1, 0.0], [-0.12, 0.07]])
+    o = np.float32([[x, y, -3.0] for x, y in offs])
+    d = np.float32([[0.0, 0.0, 1.0]] * len(offs))
+    p = R.Params(hit_list=hit_list, eps1=eps1, max_hits=0, bg=(0.25, 0.5, 0.75))
+    op = G.oracle_params(O, p)
+    out, state, status, (bvh, g, rays) = G.render(sc, o, d, p)
+    assert status == 0
+    ref, T, L = O.render_fwd(sc, o, d, op)
+    assert T[0] == 0.0 and L[0] == (4 if eps1 == 0.0 else 2)
+    assert np.abs(out - ref).max() <= 1e-5
+    rng = np.random.default_rng(90)
+    grad = np.float32(rng.normal(size=(len(offs), 3)))
+    got = _grads_gpu(R, bvh, g, rays, p, grad, state)
+    refg = O.render_bwd(sc, o, d, grad.astype(np.float64), op)
+    for k in GROUPS:
+        assert np.all(np.isfinite(got[k])), k
+    _assert_elementwise(got, refg, f"opacity 1 lists {hit_list} eps1 {eps1}")
+    # the opaque Gaussian's opacity gradient sees the colour behind it (not 0/0)
+    assert abs(refg["opacity"][1]) > 1e-3
 
 
 @pytest.mark.parametrize("max_hits,eps1", [(3, 1e-4), (0, 0.0), (512, 0.3)])
@@ -94,8 +186,10 @@ def test_gradients_under_caps(max_hits, eps1):
     cam = look_at_camera((0, 0, -3), (0, 0, 0), (0, 1, 0), 32, 32)
     o, d = pinhole_rays(cam)
     rng = np.random.default_rng(3)
-    _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)), R.Params(max_hits=max_hits, eps1=eps1),
-                 views=[(0, 32, 32)], label=f"caps {max_hits} {eps1}")
+    for hit_list in (0, 48):
+        _grad_parity(sc, o, d, rng.normal(size=(o.shape[0], 3)),
+                     R.Params(max_hits=max_hits, eps1=eps1, hit_list=hit_list), views=[(0, 32, 32)],
+                     label=f"caps {max_hits} {eps1} lists {hit_list}")
 
 
 def test_autograd_function_matches_adjoint():
@@ -105,23 +199,35 @@ def test_autograd_function_matches_adjoint():
     o, d, views = G.camera_rays(w["cams"])
     sc = w["scene"]
     params = [G.dev(a).requires_grad_(True) for a in sc.arrays()]
-    out = R.render(*params, G.dev(o), G.dev(d), R.Params(), views)
+    p = R.Params(raise_on_status=True)
+    out = R.render(*params, G.dev(o), G.dev(d), p, views)
     loss = out.abs().mean()
     loss.backward()
     torch.cuda.synchronize()
     grad = np.float32(np.sign(out.detach().cpu().numpy()) / out.numel())
     # the same adjoint called directly through the C ABI
-    p = R.Params()
     _, state, _, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
-    direct = R.render_bwd(bvh, g, rays, p, G.dev(grad), torch.from_numpy(state).cuda())
-    torch.cuda.synchronize()
-    for k, prm, dgt in zip(GROUPS, params, direct):
+    direct = _grads_gpu(R, bvh, g, rays, p, grad, state)
+    for k, prm in zip(GROUPS, params):
         a = prm.grad.cpu().numpy().astype(np.float64)
-        b = dgt.cpu().numpy().astype(np.float64)
+        b = direct[k]
         # same kernels, so equal up to float32 atomic ordering
         assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), k
-    # and the oracle agrees on the unambiguous pixels
+    # and the oracle agrees on the pixels with the oracle's hit sequence
     _grad_parity(sc, o, d, grad.astype(np.float64), p, views=views, label="autograd-ref")
+
+
+def test_autograd_raises_on_device_status():
+    """With raise_on_status the autograd Function reports a device-side error
+    (here a traversal stack of depth 1) instead of returning a silent image."""
+    print("case autograd status", flush=True)
+    G, R = _g()
+    from paper_2501_19196_amd import _lib as L
+    w = workload(1)
+    o, d, views = G.camera_rays(w["cams"])
+    params = [G.dev(a) for a in w["scene"].arrays()]
+    with pytest.raises(L.RaySplatsError, match="stack"):
+        R.render(*params, G.dev(o), G.dev(d), R.Params(stack_depth=1, raise_on_status=True), views)
 
 
 def test_persistent_backward_matches_plain():
@@ -131,20 +237,20 @@ def test_persistent_backward_matches_plain():
     o, d, views = G.camera_rays(w["cams"])
     rng = np.random.default_rng(4)
     grad = G.dev(np.float32(rng.normal(size=(o.shape[0], 3))))
-    res = []
-    for flags in (0, 2):
-        p = R.Params(flags=flags)
-        out, state, status, (bvh, g, rays) = G.render(w["scene"], o, d, p, views=views)
-        gg = R.render_bwd(bvh, g, rays, p, grad, torch.from_numpy(state).cuda())
-        torch.cuda.synchronize()
-        res.append([t.cpu().numpy() for t in gg])
-    for a, b in zip(*res):
-        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(a), 1e-12)
+    for hit_list in (0, 64):
+        res = []
+        for flags in (0, 2):
+            p = R.Params(flags=flags, hit_list=hit_list)
+            out, state, status, (bvh, g, rays) = G.render(w["scene"], o, d, p, views=views)
+            res.append(_grads_gpu(R, bvh, g, rays, p, grad, state))
+        for k in GROUPS:
+            a, b = res[0][k], res[1][k]
+            assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(a), 1e-12), (hit_list, k)
 
 
 def test_config2_l1_loss_gradients_sampled():
     """Config-2 shape: L1 loss against a target rendered from a jittered copy,
-    gradient restricted to a seeded sample of pixels (full-size render)."""
+    gradient restricted to a seeded sample of pixels."""
     print("case config2 L1 grads", flush=True)
     G, R = _g()
     w = workload(2)
@@ -157,55 +263,88 @@ def test_config2_l1_loss_gradients_sampled():
     _grad_parity(w["scene"], o[sel], d[sel], grad, R.Params(), views=None, label="config2 sampled")
 
 
-# ------------------------------------------------- stored hit lists (store vs recompute)
-
-def _fwd_bwd(R, G, sc, o, d, p, views, grad):
+def _full_size_sampled(k, n_samples, seed, hit_list, label):
+    """The full-size workload rendered and differentiated in the launch
+    configuration the benchmark times (all its views in one launch, stored
+    lists of capacity hit_list or re-traversal), with the upstream gradient of
+    a mean L1 loss kept on a seeded sample of pixels only; the oracle computes
+    the same sample's gradient pixel by pixel."""
+    G, R = _g()
+    w = workload(k)
+    o, d, views = G.camera_rays(w["cams"])
+    sc = w["scene"]
+    p = R.Params(hit_list=hit_list, flags=2 if len(views) > 1 else 0)
+    rng = np.random.default_rng(seed)
+    sel = np.sort(rng.choice(o.shape[0], n_samples, replace=False))
+    diff = _differing_pixels(sc, o[sel], d[sel], p, label)
     out, state, status, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
     assert status == 0
-    gg = R.render_bwd(bvh, g, rays, p, G.dev(np.float32(grad)), torch.from_numpy(state).cuda())
-    torch.cuda.synchronize()
-    return out, state, [t.cpu().numpy().astype(np.float64) for t in gg], bvh
+    tgt = np.float32(np.clip(out + np.float32(rng.normal(scale=0.05, size=out.shape)), 0, 1))
+    gsel = np.float32(np.sign(out[sel] - tgt[sel]) / (3.0 * o.shape[0]))
+    gsel *= (~diff)[:, None]
+    grad = np.zeros_like(out)
+    grad[sel] = gsel
+    got = _grads_gpu(R, bvh, g, rays, p, grad, state)
+    ref = O.render_bwd(sc, o[sel], d[sel], gsel.astype(np.float64), G.oracle_params(O, p))
+    _assert_elementwise(got, ref, label)
 
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("hit_list", [512, 0])
+def test_scene_scale_sampled_gradients(hit_list):
+    """1M Gaussians, 1920x1080, 8,000 sampled pixels."""
+    print("case scene-scale sampled grads", hit_list, flush=True)
+    _full_size_sampled(4, 8000, 41, hit_list, f"scene-scale 8000 px lists {hit_list}")
+
+
+@pytest.mark.timeout(600)
+def test_batch_8views_sampled_gradients():
+    """300k Gaussians (40 % flat), 8 views of uneven size in one persistent launch."""
+    print("case 8-view batch sampled grads", flush=True)
+    _full_size_sampled(3, 8000, 43, 512, "8-view batch 8000 px")
+
+
+# ------------------------------------------------- stored hit lists (store vs recompute)
 
 @pytest.mark.parametrize("cap,max_hits", [(512, 512), (64, 512), (4, 0), (16, 64)])
 def test_stored_hit_lists_match_recompute(cap, max_hits):
-    """The list-replay adjoint (with traversal for rays whose list overflows)
-    gives the recomputing adjoint's gradients; the forward is unchanged and its
-    lists hold exactly the composited ids."""
+    """The list-replay adjoint (with re-traversal for the rays of packets that
+    found the pool exhausted) gives the re-traversing adjoint's gradients; the
+    forward is unchanged and its lists hold exactly the composited ids."""
     print("case hit lists", cap, max_hits, flush=True)
     G, R = _g()
     w = workload(1)
     o, d, views = G.camera_rays(w["cams"])
     sc = w["scene"]
-    rng = np.random.default_rng(11)
-    grad = rng.normal(size=(o.shape[0], 3))
-    out0, st0, g0, _ = _fwd_bwd(R, G, sc, o, d, R.Params(max_hits=max_hits), views, grad)
-    p = R.Params(max_hits=max_hits, hit_list=cap)
-    out1, st1, g1, bvh = _fwd_bwd(R, G, sc, o, d, p, views, grad)
-    np.testing.assert_array_equal(out1, out0)
     n = o.shape[0]
-    np.testing.assert_array_equal(st1[:4 * n].reshape(n, 4), st0)
-    for k, a, b in zip(GROUPS, g1, g0):
-        assert np.linalg.norm(a - b) <= 1e-5 * max(np.linalg.norm(b), 1e-30), k
-    # the stored ids are the oracle's composited hits, in order, for rays whose hit set is unambiguous
-    raw = st1.view(np.int32)
-    base = (n * 16 + 255) // 256 * 256 // 4
-    counts = raw[base:base + n]
-    ids_off = ((n * 16 + 255) // 256 * 256 + n * 4 + 255) // 256 * 256 // 4
-    ids = raw[ids_off:ids_off + cap * n].reshape(cap, n)
+    rng = np.random.default_rng(11)
+    grad = np.float32(rng.normal(size=(n, 3)))
+    p0 = R.Params(max_hits=max_hits)
+    out0, st0, _, (bvh0, g0_, rays0) = G.render(sc, o, d, p0, views=views)
+    g0 = _grads_gpu(R, bvh0, g0_, rays0, p0, grad, st0)
+    p = R.Params(max_hits=max_hits, hit_list=cap)
+    out1, st1, status, (bvh, g1_, rays) = G.render(sc, o, d, p, views=views)
+    assert status == 0
+    g1 = _grads_gpu(R, bvh, g1_, rays, p, grad, st1)
+    np.testing.assert_array_equal(out1, out0)
+    np.testing.assert_array_equal(G.colour_state(st1, n), G.colour_state(st0, n))
+    for k in GROUPS:
+        assert np.linalg.norm(g1[k] - g0[k]) <= 1e-5 * max(np.linalg.norm(g0[k]), 1e-30), k
+    lists = R.hit_lists(rays, p, st1, cap=512)
     op = G.oracle_params(O, p)
-    unamb = _unambiguous(sc, o, d, op)
-    _, _, L = O.render_fwd(sc, o, d, op)
+    ids_o, L_o = O.render_lists(sc, o, d, op, cap=512)
+    full = lists["stored"] == lists["count"]
+    if cap == 4:
+        assert (~full).sum() > 0  # the pool ran out: those rays took the re-traversal
+    if cap == 512:
+        assert full.all()
+    unamb, _ = O.alternatives_batch(sc, o, d, op, max_events=3, cap=2)
     checked = 0
-    for r in np.nonzero(unamb)[0][::17]:
-        idx, _, _, _ = O.ray_hits(sc, o, d, int(r), op)
-        assert counts[r] == L[r], r
-        m = int(min(L[r], cap))
-        np.testing.assert_array_equal(ids[:m, r], idx[:m])
+    for r in np.nonzero((unamb == 1) & full)[0][::7]:
+        assert lists["count"][r] == L_o[r], r
+        np.testing.assert_array_equal(lists["ids"][r], ids_o[r])
         checked += 1
     assert checked > 50
-    if cap >= 64 and max_hits <= cap:
-        assert counts.max() <= cap
 
 
 def test_stored_hit_lists_oracle_parity_and_counters():
@@ -220,11 +359,12 @@ def test_stored_hit_lists_oracle_parity_and_counters():
     pc = R.Params(hit_list=512, flags=8)
     out, state, _, (bvh, g, rays) = G.render(w["scene"], o, d, pc, views=views)
     cf = R.read_counters(bvh)
-    R.render_bwd(bvh, g, rays, pc, G.dev(np.float32(rng.normal(size=(o.shape[0], 3)))),
-                 torch.from_numpy(state).cuda())
+    R.render_bwd(bvh, g, rays, pc, G.dev(np.float32(rng.normal(size=(o.shape[0], 3)))), state)
     cb = R.read_counters(bvh)
-    assert cb["r10"] == cf["lane_composited"] > 0
+    assert cb["list_composited"] == cf["lane_composited"] > 0
     assert cb["lane_composited"] == cf["lane_composited"]  # no traversal adjoint ran
+    assert cb["adjoint_packets"] == 0
+    assert cf["list_rows"] >= cf["lane_composited"] / 64
 
 
 # ------------------------------------------- the paper's gradient variant (second threshold)
@@ -240,7 +380,8 @@ def _opaque(seed=70, n=3000):
 def test_paper_gradient_matches_oracle(eps2):
     """RS_PAPER_GRADIENT: the forward image is unchanged, the second-phase
     counts equal the oracle's, and the gradients match the oracle's paper
-    variant on the unambiguous pixels (eps2 = 1 collects one hit at most)."""
+    variant element by element on the pixels whose composited sequence, count
+    and second phase are the oracle's (eps2 = 1 collects one hit at most)."""
     print("case paper gradient", eps2, flush=True)
     G, R = _g()
     sc = _opaque()
@@ -250,36 +391,27 @@ def test_paper_gradient_matches_oracle(eps2):
     n = o.shape[0]
     rng = np.random.default_rng(71)
     grad = rng.normal(size=(n, 3))
-    base = dict(eps1=2e-2, max_hits=128, hit_list=128, bg=(0.1, 0.2, 0.3))
+    base = dict(eps1=2e-2, max_hits=128, hit_list=256, bg=(0.1, 0.2, 0.3))
     out0, _, _, _ = G.render(sc, o, d, R.Params(**base), views=views)
     p = R.Params(**base, flags=16, eps2=eps2)
     out1, st, status, (bvh, g, rays) = G.render(sc, o, d, p, views=views)
     assert status == 0
     np.testing.assert_array_equal(out1, out0)
-    raw = st.view(np.int32)
-    off = (n * 16 + 255) // 256 * 256 // 4
-    packed = raw[off:off + n]
-    L_gpu, x_gpu = packed & 0xffff, packed >> 16
+    lists = R.hit_lists(rays, p, st, cap=256)
+    L_gpu, x_gpu = lists["count"], lists["extra"]
     op = G.oracle_params(O, p)
     e2 = float(np.float32(eps2))
     ref_g, x_ref, near = O.render_bwd_paper(sc, o, d, np.zeros((n, 3)), op, eps2=e2)
-    _, _, L_ref = O.render_fwd(sc, o, d, op)
-    mask = _unambiguous(sc, o, d, op) & ~near & (L_gpu == L_ref) & (x_gpu == x_ref)
-    print("rays with a second phase", int((x_ref > 0).sum()), "masked", int((~mask).sum()), "of", n, flush=True)
+    diff = _differing_pixels(sc, o, d, R.Params(**base), "paper variant")
+    same = ~diff & ~near & (x_gpu == x_ref)
+    print("rays with a second phase", int((x_ref > 0).sum()), "left out", int((~same).sum()), "of", n, flush=True)
     assert (x_ref > 0).sum() > 0.2 * n
-    assert mask.sum() > 0.8 * n
-    gm = grad * mask[:, None]
-    gg = R.render_bwd(bvh, g, rays, p, G.dev(np.float32(gm)), torch.from_numpy(st).cuda())
-    torch.cuda.synchronize()
-    got = dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in gg)))
-    ref, _, _ = O.render_bwd_paper(sc, o, d, np.float32(gm).astype(np.float64), op, eps2=e2)
-    exact = O.render_bwd(sc, o, d, np.float32(gm).astype(np.float64), op)
-    for k in GROUPS:
-        den = np.linalg.norm(ref[k])
-        e = np.linalg.norm(got[k] - ref[k]) / den
-        diff = np.linalg.norm(exact[k] - ref[k]) / den
-        print(k, f"{e:.2e} (exact vs paper {diff:.2e})", flush=True)
-        assert e <= REL, (k, e)
+    assert same.sum() > 0.9 * n
+    gm = np.float32(grad * same[:, None])
+    got = _grads_gpu(R, bvh, g, rays, p, gm, st)
+    ref, _, _ = O.render_bwd_paper(sc, o, d, gm.astype(np.float64), op, eps2=e2)
+    exact = O.render_bwd(sc, o, d, gm.astype(np.float64), op)
+    _assert_elementwise(got, ref, f"paper eps2 {eps2}")
     if eps2 == 1.0:
         assert x_ref.max() == 1
     # the variant is visible in the opacity gradients (the last composited hits)
@@ -290,13 +422,13 @@ def test_paper_gradient_matches_oracle(eps2):
 def test_scene_scale_adjoint_directional_derivative(group, eps, tol):
     """At the full scene-scale size (1M Gaussians, 1920x1080, stored lists of
     capacity 512), the adjoint of F = sum_rays <g, C> along a random direction
-    v matches the central difference of the forward, which the oracle pins on
-    sampled pixels. F is linear in the colours, so the rgb case is exact up to
-    float rounding. Opacities move T, so the opacity case turns off the eps1
-    and K_max stops (a stop that moves is a jump the difference would see):
-    every ray composites all its hits, and the rays with more than 512 take
-    the overflow path (stored hits replayed, then traversal). Directions that
-    the [0, 0.999] range of the opacities would clip are left out."""
+    v matches the central difference of the forward, a property that holds at
+    any size. F is linear in the colours, so the rgb case is exact up to float
+    rounding. Opacities move T, so the opacity case turns off the eps1 and K_max
+    stops (a stop that moves is a jump the difference would see): every ray
+    composites all its hits, so long lists exhaust the pool and those packets
+    take the re-traversal. Directions that the [0, 0.999] range of the
+    opacities would clip are left out."""
     print("case directional", group, flush=True)
     G, R = _g()
     w = workload(4)
@@ -319,9 +451,7 @@ def test_scene_scale_adjoint_directional_derivative(group, eps, tol):
         return float(np.sum(out.cpu().numpy().astype(np.float64) * g)), (bvh, gs, state)
 
     f0, (bvh, gs, state) = F(sc)
-    grads = R.render_bwd(bvh, gs, rays, p, G.dev(g), state)
-    torch.cuda.synchronize()
-    got = dict(zip(GROUPS, (t.cpu().numpy().astype(np.float64) for t in grads)))
+    got = _grads_gpu(R, bvh, gs, rays, p, g, state)
     analytic = float(np.sum(got[group] * v))
 
     def shifted(sign):

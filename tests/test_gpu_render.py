@@ -31,9 +31,14 @@ def _parity(sc, o, d, p, views=None, t_max=None, bg=None, label=""):
     print(label, {k: (v if k != "unresolved" else len(v)) for k, v in res.items()}, flush=True)
     assert not res["unresolved"], res["unresolved"][:10]
     # state carries the composited colour (with background) and the final transmittance
-    np.testing.assert_array_equal(state[:, :3], out)
+    st = G.colour_state(state, o.shape[0])
+    np.testing.assert_array_equal(st[:, :3], out)
     ok = np.abs(out - ref).max(axis=1) <= TOL
-    assert np.abs(state[ok, 3] - Tref[ok]).max() <= 1e-3 * 1.0 + 1e-5
+    if ok.any():
+        assert np.abs(st[ok, 3] - Tref[ok]).max() <= 1e-3 * 1.0 + 1e-5
+    # pixels outside the tolerance were each resolved by an alternative within rounding;
+    # they must stay rare
+    assert (~ok).mean() <= 0.01, int((~ok).sum())
     return out, ref
 
 
@@ -43,7 +48,7 @@ def test_config1_full_image():
     w = workload(1)
     o, d, views = G.camera_rays(w["cams"])
     out, ref = _parity(w["scene"], o, d, R.Params(), views=views, label="config1")
-    assert np.abs(out - ref).max() <= TOL or True
+    assert np.isfinite(out).all()
 
 
 def test_brute_force_equals_bvh_bitwise():
@@ -172,20 +177,26 @@ def test_stack_overflow_is_reported():
     assert status == L.RS_ERR_STACK_OVERFLOW
 
 
-def _sampled(k, n_samples, seed):
+def _sampled(k, n_samples, seed, params=None):
+    """Full-size workload k rendered in one launch (all its views; the batch of
+    8 views as one persistent launch), compared with the oracle on a seeded
+    sample of pixels under the acceptance protocol."""
     G, R = _g()
     w = workload(k)
     o, d, views = G.camera_rays(w["cams"])
-    out, _, status, _ = G.render(w["scene"], o, d, R.Params(), views=views)
+    p = params or R.Params(flags=2 if len(views) > 1 else 0)
+    out, _, status, _ = G.render(w["scene"], o, d, p, views=views)
     assert status == 0
+    assert np.all(np.isfinite(out)) and out.min() >= -1e-6 and out.max() <= 1.0 + 1e-5
     rng = np.random.default_rng(seed)
     sel = np.sort(rng.choice(o.shape[0], n_samples, replace=False))
-    op = G.oracle_params(O, R.Params())
+    op = G.oracle_params(O, p)
     ref, _, _ = O.render_fwd(w["scene"], o[sel], d[sel], op)
     res = O.compare_with_alternatives(out[sel], ref, w["scene"], o[sel], d[sel], op, tol=TOL)
     print(f"config{k} sampled", {k2: (v if k2 != "unresolved" else len(v)) for k2, v in res.items()}, flush=True)
     assert not res["unresolved"]
-    assert np.all(np.isfinite(out)) and out.min() >= -1e-6 and out.max() <= 1.0 + 1e-5
+    assert res["n"] - res["within"] <= 0.01 * n_samples
+    return out
 
 
 def test_config2_full_size_sampled():
@@ -193,6 +204,26 @@ def test_config2_full_size_sampled():
     _sampled(2, 1500, 5)
 
 
+@pytest.mark.timeout(900)
 def test_config4_full_size_sampled():
-    print("case config4 sampled", flush=True)
-    _sampled(4, 300, 6)
+    """1M Gaussians at 1920x1080: 65,536 seeded pixels against the oracle."""
+    print("case config4 sampled 65536", flush=True)
+    _sampled(4, 65536, 6)
+
+
+@pytest.mark.timeout(600)
+def test_batch_8views_full_size_sampled():
+    """300k Gaussians, 8 views (4 x 800x800, 4 x 400x300) in one persistent
+    launch, 16,384 seeded pixels against the oracle; the same rays rendered one
+    launch per view give the same image bit for bit."""
+    print("case config3 sampled", flush=True)
+    G, R = _g()
+    out = _sampled(3, 16384, 8)
+    w = workload(3)
+    o, d, views = G.camera_rays(w["cams"])
+    g = G.gaussians(w["scene"])
+    bvh = R.build_bvh(g, R.Params())
+    for off, vw, vh in views:
+        rays = G.rays_of(o[off:off + vw * vh], d[off:off + vw * vh], [(0, vw, vh)])
+        pv, _ = R.render_fwd(bvh, g, rays, R.Params(), want_state=False)
+        np.testing.assert_array_equal(pv.cpu().numpy(), out[off:off + vw * vh])
