@@ -365,6 +365,19 @@ size_t rs_loss_workspace_bytes(int32_t width, int32_t height);
 int rs_loss(const float *img, const float *target, int32_t width, int32_t height, const rs_loss_params *lp,
             float *loss, float *grad, void *ws, void *stream);
 
+/* rs_loss without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc). The E, F, G maps and partial sums live in a
+ * library-owned device array of rs_loss_noalloc_max_bytes() bytes (96 MiB),
+ * which every GPU the library runs on holds until the process ends; images
+ * whose rs_loss_workspace_bytes exceeds it return RS_ERR_UNSUPPORTED before
+ * anything is enqueued. Allocates nothing. All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race. Results equal rs_loss's. */
+int rs_loss_noalloc(const float *img, const float *target, int32_t width, int32_t height, const rs_loss_params *lp,
+                    float *loss, float *grad, void *stream);
+size_t rs_loss_noalloc_max_bytes(void);
+
 /* Human-readable text of a status code (static string). */
 const char *rs_status_string(int code);
 

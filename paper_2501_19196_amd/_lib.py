@@ -34,7 +34,7 @@ EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", 
            "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download",
            "rs_default_shading", "rs_build_mesh_bvh", "rs_trace_mesh", "rs_mesh_frame_bytes", "rs_render_mesh_fwd",
            "rs_render_mesh_bwd", "rs_autotune", "rs_default_loss_params", "rs_loss_workspace_bytes", "rs_loss",
-           "rs_hit_lists_download")
+           "rs_hit_lists_download", "rs_loss_noalloc", "rs_loss_noalloc_max_bytes")
 RS_TUNE_MAX = 32
 
 
@@ -153,6 +153,10 @@ def lib():
     L.rs_loss_workspace_bytes.restype = C.c_size_t
     L.rs_loss.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(rs_loss_params), P, P, P, P]
     L.rs_loss.restype = C.c_int
+    L.rs_loss_noalloc.argtypes = [P, P, C.c_int32, C.c_int32, C.POINTER(rs_loss_params), P, P, P]
+    L.rs_loss_noalloc.restype = C.c_int
+    L.rs_loss_noalloc_max_bytes.argtypes = []
+    L.rs_loss_noalloc_max_bytes.restype = C.c_size_t
     _lib = L
     return L
 

@@ -402,6 +402,22 @@ int rs_loss(const float *img, const float *target, int32_t width, int32_t height
     return launch_loss(img, target, width, height, lp, loss, grad, ws, static_cast<hipStream_t>(stream));
 }
 
+int rs_loss_noalloc(const float *img, const float *target, int32_t width, int32_t height, const rs_loss_params *lp,
+                    float *loss, float *grad, void *stream)
+{
+    if (!img || !target || !lp || !loss || width <= 0 || height <= 0) return RS_ERR_INVALID_ARG;
+    if (!(lp->lambda >= 0.0f && lp->lambda <= 1.0f) || lp->radius < 1 || lp->radius > 7 || !(lp->sigma > 0.0f))
+        return RS_ERR_INVALID_ARG;
+    if (int64_t(width) * height > (int64_t(1) << 30)) return RS_ERR_UNSUPPORTED;
+    if (loss_workspace_bytes(width, height) > loss_scratch_bytes()) return RS_ERR_UNSUPPORTED;
+    void *ws = nullptr;
+    const int e = loss_scratch(&ws);
+    if (e) return e;
+    return launch_loss(img, target, width, height, lp, loss, grad, ws, static_cast<hipStream_t>(stream));
+}
+
+size_t rs_loss_noalloc_max_bytes(void) { return loss_scratch_bytes(); }
+
 const char *rs_status_string(int code)
 {
     switch (code) {

@@ -282,6 +282,8 @@ size_t mesh_frame_bytes(int64_t n, int32_t cap, int bounces);
 size_t loss_workspace_bytes(int32_t w, int32_t h);
 int launch_loss(const float *img, const float *tgt, int32_t w, int32_t h, const rs_loss_params *lp, float *loss,
                 float *grad, void *ws, hipStream_t st);
+size_t loss_scratch_bytes();
+int loss_scratch(void **out);
 int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, const rs_shading *sh,
                     const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame, hipStream_t st);
 int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *sh, const rs_rays *rays, const rs_params *p,

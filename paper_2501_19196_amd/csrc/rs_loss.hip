@@ -10,6 +10,8 @@
 // (window sums of E, F, G, then the per-pixel gradient) and k_loss_total.
 #include <math.h>
 
+#include <mutex>
+
 #include "rs_internal.h"
 
 namespace rs {
@@ -246,6 +248,38 @@ int launch_loss(const float *img, const float *tgt, int32_t w, int32_t h, const 
     if (grad) k_ssim_grad<<<int(tiles), 256, 0, st>>>(img, tgt, efg, grad, L);
     k_loss_total<<<1, 256, 0, st>>>(partial, tiles, loss, L);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
+}
+
+// ------------------------------------------------ allocation-free variant
+
+// Device scratch of rs_loss_noalloc: a file-scope array each GPU holds for the
+// life of the process (its E, F, G maps and per-tile partial sums). Host code
+// never passes the array's name to a kernel: it takes the array's device
+// address on each device once, with hipGetSymbolAddress, and uses that.
+constexpr size_t kLossScratchBytes = size_t(96) << 20;
+static __device__ __align__(256) unsigned char scratch[kLossScratchBytes];
+
+constexpr int kMaxScratchDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxScratchDevices];
+
+size_t loss_scratch_bytes() { return kLossScratchBytes; }
+
+// The scratch array's device address on the current device (taken on the first
+// call made with that device current).
+int loss_scratch(void **out)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return RS_ERR_HIP;
+    if (dev < 0 || dev >= kMaxScratchDevices) return RS_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return RS_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return RS_OK;
 }
 
 }  // namespace rs
