@@ -68,7 +68,7 @@ def parse():
     ap.add_argument("--kbuf", type=int, default=0, help="fixed hit-buffer size (implies --no-autotune)")
     ap.add_argument("--persistent", action="store_true", help="persistent grid (implies --no-autotune)")
     ap.add_argument("--tile-width", type=int, default=0, help="packet tile width (implies --no-autotune)")
-    ap.add_argument("--hit-list", type=int, default=512,
+    ap.add_argument("--hit-list", type=int, default=64,
                     help="stored hit-list pool, slots per ray (0 = the adjoint re-traverses the BVH)")
     ap.add_argument("--paper-gradient", action="store_true",
                     help="the paper's backward variant (second threshold eps2 = --eps2)")

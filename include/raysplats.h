@@ -122,7 +122,7 @@ typedef struct {
  * with C > 0 the forward also records the ids of the Gaussians each ray
  * composites, in a pool of C 4-byte slots per ray on average inside the ray
  * state (a packet of 64 rays takes one row of 64 slots per compositing step of
- * its wavefront, from chunks of 16 rows), and the adjoint replays those lists
+ * its wavefront, from chunks of 8 rows), and the adjoint replays those lists
  * instead of traversing the BVH again. The rays of a packet that finds the pool
  * exhausted are traversed again by the adjoint. The gradients are the same (up to
  * float atomic order). The mesh renders keep one pool for all their ray sets in
@@ -164,7 +164,7 @@ size_t rs_bvh_workspace_bytes(int64_t n_gaussians);
  * 16 bytes per ray that the adjoint starts from (the last composited hit and
  * where T reached 0) and, when p->hit_list = C > 0, 16 bytes of list
  * bookkeeping per ray plus the stored-list pool (C slots of 4 bytes per ray on
- * average, in whole chunks of 4 KiB, after a 256-byte header). */
+ * average, in whole chunks of 2 KiB, after a 256-byte header). */
 size_t rs_ray_state_bytes(int64_t n_rays, const rs_params *p);
 
 /* Build the BVH: 30-bit Morton codes of the means, LDS radix sort, leaf boxes

@@ -192,7 +192,7 @@ struct SetState {
 // step; rows live in chunks of kListRows, linked backwards per packet. The
 // pool header holds the chunk counter (64-bit) and a flag set when a packet
 // found the pool exhausted (its later rows are not stored).
-constexpr int kListRows = 16;
+constexpr int kListRows = 8;
 constexpr uint32_t kListIdle = 0xffffffffu;
 constexpr uint32_t kListSecond = 0x80000000u;
 struct ListPool {
