@@ -384,14 +384,25 @@ const char *rs_status_string(int code);
 /* Copy the stored hit lists of a ray state written by rs_render_fwd (with the
  * same rays and params, p->hit_list > 0) to host memory; synchronises
  * `stream`. Inspection helper for tests and tools, not part of the method.
- *  count[n]   hits each ray composited
- *  stored[n]  how many of them its list holds (fewer when the pool ran out)
- *  extra[n]   ids the paper variant collected after the eps1 stop, else 0
- *  ids        [n][cap]: per ray its stored ids in compositing order, then the
+ *  rays_sel   host int64 [n_sel] ray indices to copy (NULL: every ray, n_sel ignored)
+ *  count      [m] hits each ray composited (m = n_sel, or rays->n)
+ *  stored     [m] how many of them its list holds (fewer when the pool ran out)
+ *  extra      [m] ids the paper variant collected after the eps1 stop, else 0
+ *  ids        [m][cap]: per ray its stored ids in compositing order, then the
  *             collected ones; -1 after the last (entries beyond cap dropped)
  * Any output pointer may be NULL (ids needs cap > 0). */
-int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, int32_t *count,
-                          int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap, void *stream);
+int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, const int64_t *rays_sel,
+                          int64_t n_sel, int32_t *count, int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap,
+                          void *stream);
+
+/* The same for ray set `set` of a mesh frame written by rs_render_mesh_fwd
+ * (same rays, params and shading, p->hit_list > 0): sets 0..B are the path
+ * rays of levels 0..B (0: the camera rays), sets B+1..2B the shadow rays of
+ * levels 0..B-1, B = sh->max_bounces. Rays of a set that were not spawned
+ * composite nothing. */
+int rs_mesh_hit_lists_download(const rs_rays *rays, const rs_params *p, const rs_shading *sh, const void *frame,
+                               int32_t set, const int64_t *rays_sel, int64_t n_sel, int32_t *count, int32_t *stored,
+                               int32_t *ids, int32_t cap, void *stream);
 
 /* Copy the built BVH to host memory for inspection (synchronises `stream`).
  * Any pointer may be NULL. codes[n] (uint32, sorted Morton codes),

@@ -34,7 +34,7 @@ EXPORTS = ("rs_default_params", "rs_bvh_workspace_bytes", "rs_ray_state_bytes", 
            "rs_render_bwd", "rs_read_status", "rs_read_counters", "rs_status_string", "rs_bvh_download",
            "rs_default_shading", "rs_build_mesh_bvh", "rs_trace_mesh", "rs_mesh_frame_bytes", "rs_render_mesh_fwd",
            "rs_render_mesh_bwd", "rs_autotune", "rs_default_loss_params", "rs_loss_workspace_bytes", "rs_loss",
-           "rs_hit_lists_download", "rs_loss_noalloc", "rs_loss_noalloc_max_bytes")
+           "rs_hit_lists_download", "rs_mesh_hit_lists_download", "rs_loss_noalloc", "rs_loss_noalloc_max_bytes")
 RS_TUNE_MAX = 32
 
 
@@ -127,8 +127,12 @@ def lib():
     L.rs_status_string.restype = C.c_char_p
     L.rs_bvh_download.argtypes = [C.POINTER(rs_bvh), P, P, P, P, P, P, P]
     L.rs_bvh_download.restype = C.c_int
-    L.rs_hit_lists_download.argtypes = [C.POINTER(rs_rays), C.POINTER(rs_params), P, P, P, P, P, C.c_int32, P]
+    L.rs_hit_lists_download.argtypes = [C.POINTER(rs_rays), C.POINTER(rs_params), P, P, C.c_int64, P, P, P, P,
+                                        C.c_int32, P]
     L.rs_hit_lists_download.restype = C.c_int
+    L.rs_mesh_hit_lists_download.argtypes = [C.POINTER(rs_rays), C.POINTER(rs_params), C.POINTER(rs_shading), P,
+                                             C.c_int32, P, C.c_int64, P, P, P, C.c_int32, P]
+    L.rs_mesh_hit_lists_download.restype = C.c_int
     L.rs_default_shading.argtypes = [C.POINTER(rs_shading)]
     L.rs_default_shading.restype = None
     L.rs_build_mesh_bvh.argtypes = [C.POINTER(rs_mesh), P, C.c_size_t, C.POINTER(rs_bvh), P]

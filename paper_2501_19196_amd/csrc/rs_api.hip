@@ -494,21 +494,19 @@ static int ray_lane(const rs_rays *rays, int tile_shift, int64_t r)
     return 0;
 }
 
-int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, int32_t *count,
-                          int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap, void *stream)
+// Host copies of stored lists (the list bookkeeping of a ray set and its pool).
+static int lists_download(const rs_rays *rays, int tile_shift, const int4 *dev_list, const ListPool &P,
+                          const int64_t *sel, int64_t n_sel, int32_t *count, int32_t *stored, int32_t *extra,
+                          int32_t *ids, int32_t cap)
 {
-    int e = check_rays(rays);
-    if (e) return e;
-    if ((e = check_params(p))) return e;
-    if (!ray_state || p->hit_list <= 0 || cap < 0 || (ids && cap == 0)) return RS_ERR_INVALID_ARG;
-    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RS_ERR_HIP;
     const int64_t n = rays->n;
-    if (n == 0) return RS_OK;
-    const StateLayout SL = state_layout(n, p->hit_list);
-    const char *base = static_cast<const char *>(ray_state);
+    const int64_t m = sel ? n_sel : n;
+    if (m <= 0 || n == 0) return RS_OK;
+    if (sel)
+        for (int64_t i = 0; i < m; ++i)
+            if (sel[i] < 0 || sel[i] >= n) return RS_ERR_INVALID_ARG;
     std::vector<int4> li(static_cast<size_t>(n));
-    if (hipMemcpy(li.data(), base + SL.list, size_t(n) * 16, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
-    ListPool P = list_pool_at(const_cast<char *>(base) + SL.pool, SL.chunks);
+    if (hipMemcpy(li.data(), dev_list, size_t(n) * 16, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     unsigned long long taken = 0;
     if (hipMemcpy(&taken, P.hdr, 8, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     const int64_t used = int64_t(taken < (unsigned long long)P.chunks ? taken : (unsigned long long)P.chunks);
@@ -520,12 +518,12 @@ int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *r
             hipSuccess)
             return RS_ERR_HIP;
     }
-    const int ts = tile_shift_of(p);
     std::unordered_map<int32_t, std::vector<int32_t>> chains;  // a packet's chunks, first to last
-    for (int64_t r = 0; r < n; ++r) {
+    for (int64_t i = 0; i < m; ++i) {
+        const int64_t r = sel ? sel[i] : i;
         const int4 L = li[size_t(r)];
-        if (count) count[r] = L.x;
-        if (stored) stored[r] = L.y;
+        if (count) count[i] = L.x;
+        if (stored) stored[i] = L.y;
         int32_t x = 0, w = 0;
         if (L.w > 0 && L.z >= 0 && L.z < used) {
             auto it = chains.find(L.z);
@@ -537,21 +535,58 @@ int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *r
                 it = chains.emplace(L.z, std::move(fw)).first;
             }
             const std::vector<int32_t> &ch = it->second;
-            const int lane = ray_lane(rays, ts, r);
+            const int lane = ray_lane(rays, tile_shift, r);
             for (int32_t row = 0; row < L.w && size_t(row / kListRows) < ch.size(); ++row) {
                 const uint32_t v =
                     slots[(size_t(ch[size_t(row / kListRows)]) * kListRows + size_t(row % kListRows)) * kWave + lane];
                 if (v == kListIdle) continue;
                 if (v & kListSecond) ++x;
-                if (ids && w < cap) ids[r * int64_t(cap) + w] = int32_t(v & ~kListSecond);
+                if (ids && w < cap) ids[i * int64_t(cap) + w] = int32_t(v & ~kListSecond);
                 ++w;
             }
         }
         if (ids)
-            for (int32_t k = w; k < cap; ++k) ids[r * int64_t(cap) + k] = -1;
-        if (extra) extra[r] = x;
+            for (int32_t k = w; k < cap; ++k) ids[i * int64_t(cap) + k] = -1;
+        if (extra) extra[i] = x;
     }
     return RS_OK;
+}
+
+int rs_hit_lists_download(const rs_rays *rays, const rs_params *p, const void *ray_state, const int64_t *rays_sel,
+                          int64_t n_sel, int32_t *count, int32_t *stored, int32_t *extra, int32_t *ids, int32_t cap,
+                          void *stream)
+{
+    int e = check_rays(rays);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if (!ray_state || p->hit_list <= 0 || cap < 0 || (ids && cap == 0) || (rays_sel && n_sel < 0))
+        return RS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RS_ERR_HIP;
+    if (rays->n == 0) return RS_OK;
+    const StateLayout SL = state_layout(rays->n, p->hit_list);
+    char *base = const_cast<char *>(static_cast<const char *>(ray_state));
+    return lists_download(rays, tile_shift_of(p), reinterpret_cast<const int4 *>(base + SL.list),
+                          list_pool_at(base + SL.pool, SL.chunks), rays_sel, n_sel, count, stored, extra, ids, cap);
+}
+
+int rs_mesh_hit_lists_download(const rs_rays *rays, const rs_params *p, const rs_shading *sh, const void *frame,
+                               int32_t set, const int64_t *rays_sel, int64_t n_sel, int32_t *count, int32_t *stored,
+                               int32_t *ids, int32_t cap, void *stream)
+{
+    int e = check_rays(rays);
+    if (e) return e;
+    if ((e = check_params(p))) return e;
+    if ((e = check_shading(sh))) return e;
+    if (!frame || p->hit_list <= 0 || cap < 0 || (ids && cap == 0) || (rays_sel && n_sel < 0))
+        return RS_ERR_INVALID_ARG;
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess) return RS_ERR_HIP;
+    if (rays->n == 0) return RS_OK;
+    SetState st;
+    ListPool pool;
+    if ((e = mesh_frame_set(const_cast<char *>(static_cast<const char *>(frame)), rays->n, p->hit_list,
+                            sh->max_bounces, set, &st, &pool)))
+        return e;
+    return lists_download(rays, tile_shift_of(p), st.list, pool, rays_sel, n_sel, count, stored, nullptr, ids, cap);
 }
 
 }  // extern "C"

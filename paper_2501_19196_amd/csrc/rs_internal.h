@@ -279,6 +279,7 @@ int launch_build_mesh(const rs_mesh *m, char *ws, hipStream_t st);
 int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limit, int any_hit, int tile_shift, float *t_hit,
                       int32_t *tri, hipStream_t st);
 size_t mesh_frame_bytes(int64_t n, int32_t cap, int bounces);
+int mesh_frame_set(char *frame, int64_t n, int32_t cap, int bounces, int set, SetState *st, ListPool *pool);
 size_t loss_workspace_bytes(int32_t w, int32_t h);
 int launch_loss(const float *img, const float *tgt, int32_t w, int32_t h, const rs_loss_params *lp, float *loss,
                 float *grad, void *ws, hipStream_t st);
@@ -288,6 +289,6 @@ int launch_mesh_fwd(const BvhDesc &G, const BvhDesc &M, const rs_gaussians *g, c
                     const rs_rays *rays, const rs_params *p, float *out_rgb, void *frame, hipStream_t st);
 int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *sh, const rs_rays *rays, const rs_params *p,
                     const float *grad, void *frame, const rs_grads *grads, hipStream_t st);
-void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st);
+void scatter_gacc(const BvhDesc &D, const float *quat, const rs_grads *grads, hipStream_t st);
 
 }  // namespace rs

@@ -459,6 +459,16 @@ int launch_trace_mesh(const BvhDesc &M, const rs_rays *rays, const float *t_limi
 
 size_t mesh_frame_bytes(int64_t n, int32_t cap, int bounces) { return frame_layout(nullptr, n, cap, bounces).total; }
 
+// The state and list pool of ray set `set` of a frame (0..B: path levels, B+1..2B: shadow levels).
+int mesh_frame_set(char *frame, int64_t n, int32_t cap, int bounces, int set, SetState *st, ListPool *pool)
+{
+    if (set < 0 || set > 2 * bounces) return RS_ERR_INVALID_ARG;
+    const Frame F = frame_layout(frame, n, cap, bounces);
+    *st = set <= bounces ? F.P[set].st : F.S[set - bounces - 1].st;
+    *pool = F.pool;
+    return RS_OK;
+}
+
 static ShadeConst shade_const(const rs_shading *sh, const rs_params *p)
 {
     ShadeConst C;
@@ -579,7 +589,7 @@ int launch_mesh_bwd(const BvhDesc &G, const rs_gaussians *g, const rs_shading *s
         }
         if ((e = launch_sets(G, g, &ps, nsets, S, F.pool, Pass::AdjointTraverse, st))) return e;
     }
-    scatter_gacc(G, grads, st);
+    scatter_gacc(G, g->quat, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 

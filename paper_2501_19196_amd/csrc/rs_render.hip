@@ -69,10 +69,11 @@ struct RenderParams {
 // Gaussians (one scale -> 0) lose no precision to cancellation. The nearer
 // root is t1 = -b/a - sqrt((Q - h^2)/a) for b = <o',d'> >= 0 and the Viete
 // form (|o'|^2 - Q) / (a t*) otherwise (Prop. 1, App. A.1).
-// Intermediates of the test that the adjoint of a hit reuses (world offset
-// x = o - m, whitened direction d', scaled cross product u, b = <o',d'>, 1/a).
+// Intermediates of the test that the adjoint of a hit reuses (the body-frame
+// offset y = R^T (o - m) and direction e = R^T d, the scaled cross product u,
+// b = <o',d'>, 1/a).
 struct HitGeom {
-    float xx, xy, xz, d0, d1, d2, u0, u1, u2, b, ia;
+    float y0, y1, y2, e0, e1, e2, u0, u1, u2, b, ia;
 };
 
 __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
@@ -101,7 +102,7 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float uu = u0 * u0 + u1 * u1 + u2 * u2;
     const float ia = __builtin_amdgcn_rcpf(a);
     h2 = uu * ia;
-    G = HitGeom{xx, xy, xz, d0, d1, d2, u0, u1, u2, b, ia};
+    G = HitGeom{y0, y1, y2, e0, e1, e2, u0, u1, u2, b, ia};
     // both root forms for every lane and a select, no divergent branch (t1 is only used
     // where the ray hits, h2 <= Q, and there the chosen form is the same arithmetic)
     const float sq = __builtin_amdgcn_sqrtf((Q - h2) * ia);  // hardware square root (1 ulp)
@@ -195,74 +196,47 @@ __device__ inline bool stop_after(const Accum &A, const RenderParams &P)
 
 // --------------------------------------------------------------- adjoint
 
-// Gradient of h^2 (and so of alpha = opacity exp(-h^2/2)) for one hit.
-// With p = o' - (b/a) d' (whitened closest point, obtained without
-// cancellation as p = (d' x (o' x d')) / a) and q_w = x - (b/a) d:
-//   dh2/dm = -2 R D p,  dh2/ds_k = -2 D_k p_k^2,  dh2/dR = 2 q_w (D p)^T,
-// and dh2/dq follows from R(q) = P(q)/|q|^2, P the homogeneous quadratic
-// form, as (<dh2/dR, dP/dq_j> - 2 q_j <dh2/dR, R>) / |q|^2. These are the
-// App. A.6 expressions regrouped: dh2/dtheta = 2<p, do'> - 2(b/a)<p, dd'>.
+// Gradient of h^2 (and so of alpha = opacity exp(-h^2/2)) for one hit, in the
+// Gaussian's body frame. With p = o' - (b/a) d' (the whitened closest point,
+// obtained without cancellation as p = (d' x u) / a, u = o' x d'), D = diag(1/s)
+// and y_w = y - (b/a) e the body-frame closest-approach offset, App. A.6 gives
+//   dh2/dm = -2 R D p,   dh2/ds_k = -2 D_k p_k^2,   dh2/dR = 2 R y_w (D p)^T.
+// The rotation enters only through R^T dh2/dR, whose antisymmetric part is the
+// angular vector w = 2 (D p) x y_w: a change dR = R [dtheta]x changes h2 by
+// <w, dtheta>. So a hit contributes, per Gaussian,
+//   acc_m = gh D p,  acc_s = -2 gh D_k p_k^2,  acc_w = 2 gh (D p) x y_w,
+// (gh = dL/dh2), and k_scatter_grads applies R and the quaternion map once per
+// Gaussian: dL/dm = -2 R acc_m, dL/dq = (2/|q|) E(q/|q|)^T acc_w, where
+// dtheta = (2/|q|) E(n) dq, E(n) = [-v | w I - [v]x] for n = (w, v).
 struct GradOut {
-    float v[14];  // mean 3, scale 3, quat 4, opacity 1, rgb 3
+    float v[13];  // mean (body frame) 3, scale 3, angular 3, opacity 1, rgb 3
 };
 
-__device__ inline void grad_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const HitGeom &g,
-                                float h2, const float *__restrict__ quat, uint32_t gid, float dLda, float alpha,
-                                GradOut &G)
+__device__ inline void grad_hit(const float4 r2, const HitGeom &g, float h2, float dLda, float alpha, GradOut &G)
 {
-    // the test's own intermediates (same rounding as the alpha being differentiated)
-    const float xx = g.xx, xy = g.xy, xz = g.xz, d0 = g.d0, d1 = g.d1, d2 = g.d2, u0 = g.u0, u1 = g.u1, u2 = g.u2;
-    const float b = g.b, ia = g.ia;
-    const float a00 = r0.x, a01 = r0.y, a02 = r0.z, a10 = r0.w, a11 = r1.x, a12 = r1.y, a20 = r1.z, a21 = r1.w,
-                a22 = r2.x;
     const float D0 = r2.y, D1 = r2.z, D2 = r2.w;
+    const float d0 = D0 * g.e0, d1 = D1 * g.e1, d2 = D2 * g.e2;
     // p = (d' x u) / a
-    const float p0 = (d1 * u2 - d2 * u1) * ia;
-    const float p1 = (d2 * u0 - d0 * u2) * ia;
-    const float p2 = (d0 * u1 - d1 * u0) * ia;
-    const float ba = b * ia;
-    const float qx = xx - ba * ray.dx, qy = xy - ba * ray.dy, qz = xz - ba * ray.dz;
+    const float p0 = (d1 * g.u2 - d2 * g.u1) * g.ia;
+    const float p1 = (d2 * g.u0 - d0 * g.u2) * g.ia;
+    const float p2 = (d0 * g.u1 - d1 * g.u0) * g.ia;
     const float Dp0 = D0 * p0, Dp1 = D1 * p1, Dp2 = D2 * p2;
+    const float ba = g.b * g.ia;
+    const float w0 = g.y0 - ba * g.e0, w1 = g.y1 - ba * g.e1, w2 = g.y2 - ba * g.e2;
     const float gh = dLda * (-0.5f * alpha);  // dL/dh2
-    // z = R Dp; R_ik = RT_ki
-    const float z0 = a00 * Dp0 + a10 * Dp1 + a20 * Dp2;
-    const float z1 = a01 * Dp0 + a11 * Dp1 + a21 * Dp2;
-    const float z2 = a02 * Dp0 + a12 * Dp1 + a22 * Dp2;
-    G.v[0] = gh * (-2.0f * z0);
-    G.v[1] = gh * (-2.0f * z1);
-    G.v[2] = gh * (-2.0f * z2);
+    G.v[0] = gh * Dp0;
+    G.v[1] = gh * Dp1;
+    G.v[2] = gh * Dp2;
     G.v[3] = gh * (-2.0f * Dp0 * p0);
     G.v[4] = gh * (-2.0f * Dp1 * p1);
     G.v[5] = gh * (-2.0f * Dp2 * p2);
-    // quaternion
-    const float4 q = reinterpret_cast<const float4 *>(quat)[gid];
-    const float qa = q.x, qb = q.y, qc = q.z, qd = q.w;
-    const float nq = qa * qa + qb * qb + qc * qc + qd * qd;
-    // <G_R, M> = 2 q_w^T M Dp for G_R = 2 q_w Dp^T
-    const float qRz = qx * z0 + qy * z1 + qz * z2;  // q_w^T R Dp
-    // dP/da = 2[[a,-d,c],[d,a,-b],[-c,b,a]] etc.; M Dp for each
-    const float ma0 = qa * Dp0 - qd * Dp1 + qc * Dp2, ma1 = qd * Dp0 + qa * Dp1 - qb * Dp2,
-                ma2 = -qc * Dp0 + qb * Dp1 + qa * Dp2;
-    const float mb0 = qb * Dp0 + qc * Dp1 + qd * Dp2, mb1 = qc * Dp0 - qb * Dp1 - qa * Dp2,
-                mb2 = qd * Dp0 + qa * Dp1 - qb * Dp2;
-    const float mc0 = -qc * Dp0 + qb * Dp1 + qa * Dp2, mc1 = qb * Dp0 + qc * Dp1 + qd * Dp2,
-                mc2 = -qa * Dp0 + qd * Dp1 - qc * Dp2;
-    const float md0 = -qd * Dp0 - qa * Dp1 + qb * Dp2, md1 = qa * Dp0 - qd * Dp1 + qc * Dp2,
-                md2 = qb * Dp0 + qc * Dp1 + qd * Dp2;
-    const float sa = 2.0f * (qx * ma0 + qy * ma1 + qz * ma2);
-    const float sb = 2.0f * (qx * mb0 + qy * mb1 + qz * mb2);
-    const float scq = 2.0f * (qx * mc0 + qy * mc1 + qz * mc2);
-    const float sd = 2.0f * (qx * md0 + qy * md1 + qz * md2);
-    const float inq = 1.0f / nq;
-    // dh2/dq_j = 2 (q_w^T dP_j Dp - 2 q_j q_w^T R Dp) / |q|^2
-    G.v[6] = gh * 2.0f * (sa - 2.0f * qa * qRz) * inq;
-    G.v[7] = gh * 2.0f * (sb - 2.0f * qb * qRz) * inq;
-    G.v[8] = gh * 2.0f * (scq - 2.0f * qc * qRz) * inq;
-    G.v[9] = gh * 2.0f * (sd - 2.0f * qd * qRz) * inq;
+    const float c = 2.0f * gh;
+    G.v[6] = c * (Dp1 * w2 - Dp2 * w1);
+    G.v[7] = c * (Dp2 * w0 - Dp0 * w2);
+    G.v[8] = c * (Dp0 * w1 - Dp1 * w0);
     // opacity: alpha = opacity * exp(-h2/2)
-    G.v[10] = dLda * __expf(-0.5f * h2);
+    G.v[9] = dLda * __expf(-0.5f * h2);
 }
-
 
 // ----------------------------------------------------------------- kernel
 
@@ -279,7 +253,7 @@ struct RaySet {
 };
 
 struct Ptrs {
-    const float *quat, *rgb;
+    const float *rgb;
     RaySet set[kMaxSets];
     int32_t *status;
     uint32_t *queue;  // XCD queue counters (kXcdQueues)
@@ -478,23 +452,22 @@ __device__ inline void back_over(Back &B, float al, float cr, float cg, float cb
 // instruction adds each Gaussian's totals to its 64-byte accumulator line (four
 // Gaussians per instruction).
 template <bool COUNT>
-__device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, const Ray &ray, const HitData &H,
-                                   float Tk, const Back &B, const LaneGrad &Gd, bool zc, const float *__restrict__ quat,
-                                   float *gacc, int lane, uint64_t &c_group)
+__device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, const HitData &H, float Tk,
+                                   const Back &B, const LaneGrad &Gd, bool zc, float *gacc, int lane, uint64_t &c_group)
 {
     GradOut G;
 #pragma unroll
-    for (int v = 0; v < 14; ++v) G.v[v] = 0.0f;
+    for (int v = 0; v < 13; ++v) G.v[v] = 0.0f;
     if (act) {
         const float dLda = Tk * (Gd.gr * (H.cr - B.Sr) + Gd.gg * (H.cg - B.Sg) + Gd.gb * (H.cb - B.Sb));
-        grad_hit(ray, H.r0, H.r1, H.r2, H.g, H.h2, quat, gid, dLda, H.al, G);
+        grad_hit(H.r2, H.g, H.h2, dLda, H.al, G);
         const float wgt = H.al * Tk;
-        G.v[11] = zc ? 0.0f : Gd.gr * wgt;
-        G.v[12] = zc ? 0.0f : Gd.gg * wgt;
-        G.v[13] = zc ? 0.0f : Gd.gb * wgt;
+        G.v[10] = zc ? 0.0f : Gd.gr * wgt;
+        G.v[11] = zc ? 0.0f : Gd.gg * wgt;
+        G.v[12] = zc ? 0.0f : Gd.gb * wgt;
     }
     // Lanes holding the same Gaussian form a group; groups are numbered in order and each
-    // group's lanes store their 14 values in consecutive LDS rows. Then 16-lane segments sum
+    // group's lanes store their 13 values in consecutive LDS rows. Then 16-lane segments sum
     // one group's rows each, so one atomic instruction adds the totals of four Gaussians (one
     // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
     // operations complete in order.
@@ -518,12 +491,12 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
     if (act) {
         float *r = rows + 16 * mypos;
 #pragma unroll
-        for (int v = 0; v < 14; ++v) r[v] = G.v[v];
+        for (int v = 0; v < 13; ++v) r[v] = G.v[v];
     }
     const int v = lane & 15;
     for (int b = 0; b < ng; b += 4) {
         const int gi = b + (lane >> 4);
-        if (gi < ng && v < 14) {
+        if (gi < ng && v < 13) {
             const int4 gd = groups[gi];
             float t = rows[16 * gd.y + v];
             for (int j = 1; j < gd.z; ++j) t += rows[16 * (gd.y + j) + v];
@@ -1005,7 +978,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 HitData H;
                 recompute_hit(act, gid, ray, records, inv, ptr.rgb, zc, P.Q, H);
                 const float Tk = back_T(B, H.al);
-                adjoint_hit<COUNT>(act, act_mask, gid, ray, H, Tk, B, Gd, zc, ptr.quat, ptr.gacc, lane, c_group);
+                adjoint_hit<COUNT>(act, act_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
                 if (act) {
                     back_over(B, H.al, H.cr, H.cg, H.cb);
                     B.T = Tk;
@@ -1080,10 +1053,17 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
         const int32_t rows = __builtin_amdgcn_readfirstlane(li.w);
         int32_t chunk = __builtin_amdgcn_readfirstlane(li.z);
         if (!wave_ballot(live)) continue;
+        // the entry of the next row (back to front) is loaded one row ahead
+        uint32_t e_next = live && rows > 0
+                              ? pool.slots[(int64_t(chunk) * kListRows + ((rows - 1) & (kListRows - 1))) * kWave + lane]
+                              : kListIdle;
         for (int32_t row = rows - 1; row >= 0; --row) {
-            if ((row & (kListRows - 1)) == kListRows - 1 && row != rows - 1) chunk = pool.prev[chunk];
-            const uint32_t e =
-                live ? pool.slots[(int64_t(chunk) * kListRows + (row & (kListRows - 1))) * kWave + lane] : kListIdle;
+            const uint32_t e = e_next;
+            if (row > 0) {
+                if ((row & (kListRows - 1)) == 0) chunk = pool.prev[chunk];
+                e_next = live ? pool.slots[(int64_t(chunk) * kListRows + ((row - 1) & (kListRows - 1))) * kWave + lane]
+                              : kListIdle;
+            }
             const bool act = e != kListIdle;
             if (!wave_ballot(act)) continue;
             const bool comp = act && e < kListSecond;
@@ -1094,7 +1074,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
             const uint64_t comp_mask = wave_ballot(comp);
             if (COUNT) c_lcomp += __popcll(comp_mask);
             if (comp_mask)
-                adjoint_hit<COUNT>(comp, comp_mask, gid, LR.ray, H, Tk, B, Gd, zc, ptr.quat, ptr.gacc, lane, c_group);
+                adjoint_hit<COUNT>(comp, comp_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
             if (act) back_over(B, H.al, H.cr, H.cg, H.cb);
             if (comp) {
                 B.T = Tk;
@@ -1118,30 +1098,48 @@ __global__ void k_zero_f32(float *p, int64_t n)
     for (; i < n; i += stride) p[i] = 0.0f;
 }
 
-// Accumulator (16 floats per Gaussian: mean 3, scale 3, quat 4, opacity 1,
-// rgb 3, 2 unused) -> the caller's gradient arrays.
-__global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict__ gacc, int64_t n, float *d_mean,
-                                                       float *d_scale, float *d_quat, float *d_opacity, float *d_rgb)
+// Accumulator (16 floats per Gaussian: body-frame mean 3, scale 3, angular 3,
+// opacity 1, rgb 3, 3 unused) -> the caller's gradient arrays: dL/dm = -2 R acc_m
+// and dL/dq = (2/|q|) E(q/|q|)^T acc_w (see grad_hit), with R^T from the
+// Gaussian's record (the rotation the renders used).
+__global__ __launch_bounds__(256) void k_scatter_grads(const float4 *__restrict__ gacc, const float4 *__restrict__ records,
+                                                       const int32_t *__restrict__ inv, const float *__restrict__ quat,
+                                                       int64_t n, float *d_mean, float *d_scale, float *d_quat,
+                                                       float *d_opacity, float *d_rgb)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float4 a = gacc[4 * i], b = gacc[4 * i + 1], c = gacc[4 * i + 2], d = gacc[4 * i + 3];
+    const float am0 = a.x, am1 = a.y, am2 = a.z, w0 = b.z, w1 = b.w, w2 = c.x;
     if (d_mean) {
-        d_mean[3 * i] = a.x;
-        d_mean[3 * i + 1] = a.y;
-        d_mean[3 * i + 2] = a.z;
+        // R = (R^T)^T: dm_k = -2 sum_j RT_jk am_j
+        const int32_t js = inv[i];
+        const float4 r0 = records[4 * js], r1 = records[4 * js + 1], r2 = records[4 * js + 2];
+        const float t00 = r0.x, t01 = r0.y, t02 = r0.z, t10 = r0.w, t11 = r1.x, t12 = r1.y, t20 = r1.z, t21 = r1.w,
+                    t22 = r2.x;
+        d_mean[3 * i] = -2.0f * (t00 * am0 + t10 * am1 + t20 * am2);
+        d_mean[3 * i + 1] = -2.0f * (t01 * am0 + t11 * am1 + t21 * am2);
+        d_mean[3 * i + 2] = -2.0f * (t02 * am0 + t12 * am1 + t22 * am2);
     }
     if (d_scale) {
         d_scale[3 * i] = a.w;
         d_scale[3 * i + 1] = b.x;
         d_scale[3 * i + 2] = b.y;
     }
-    if (d_quat) reinterpret_cast<float4 *>(d_quat)[i] = make_float4(b.z, b.w, c.x, c.y);
-    if (d_opacity) d_opacity[i] = c.z;
+    if (d_quat) {
+        const float4 q = reinterpret_cast<const float4 *>(quat)[i];
+        const float nq = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+        const float in = 1.0f / nq, k = 2.0f * in;
+        const float qw = q.x * in, vx = q.y * in, vy = q.z * in, vz = q.w * in;
+        reinterpret_cast<float4 *>(d_quat)[i] =
+            make_float4(-k * (vx * w0 + vy * w1 + vz * w2), k * (qw * w0 + (vy * w2 - vz * w1)),
+                        k * (qw * w1 + (vz * w0 - vx * w2)), k * (qw * w2 + (vx * w1 - vy * w0)));
+    }
+    if (d_opacity) d_opacity[i] = c.y;
     if (d_rgb) {
-        d_rgb[3 * i] = c.w;
-        d_rgb[3 * i + 1] = d.x;
-        d_rgb[3 * i + 2] = d.y;
+        d_rgb[3 * i] = c.z;
+        d_rgb[3 * i + 1] = c.w;
+        d_rgb[3 * i + 2] = d.x;
     }
 }
 
@@ -1200,13 +1198,14 @@ void zero_gacc(const BvhDesc &D, hipStream_t st)
     zero(reinterpret_cast<float *>(D.ws + L.gacc), 16 * D.n, st);
 }
 
-void scatter_gacc(const BvhDesc &D, const rs_grads *grads, hipStream_t st)
+void scatter_gacc(const BvhDesc &D, const float *quat, const rs_grads *grads, hipStream_t st)
 {
     if (D.n <= 0) return;
     Layout L = make_layout(D.n);
-    k_scatter_grads<<<int((D.n + 255) / 256), 256, 0, st>>>(reinterpret_cast<const float4 *>(D.ws + L.gacc), D.n,
-                                                             grads->d_mean, grads->d_scale, grads->d_quat,
-                                                             grads->d_opacity, grads->d_rgb);
+    k_scatter_grads<<<int((D.n + 255) / 256), 256, 0, st>>>(
+        reinterpret_cast<const float4 *>(D.ws + L.gacc), reinterpret_cast<const float4 *>(D.ws + L.records),
+        reinterpret_cast<const int32_t *>(D.ws + L.inv), quat, D.n, grads->d_mean, grads->d_scale, grads->d_quat,
+        grads->d_opacity, grads->d_rgb);
 }
 
 // One launch over up to kMaxSets ray sets sharing a layout (same count, same views).
@@ -1242,7 +1241,6 @@ int launch_sets(const BvhDesc &D, const rs_gaussians *g, const rs_params *p, int
     P.chunk = (P.n_packets + kXcdQueues - 1) / kXcdQueues;
 
     Ptrs ptr{};
-    ptr.quat = g->quat;
     ptr.rgb = g->rgb;
     for (int k = 0; k < kMaxSets; ++k) {
         const SetDesc &E = sets[k < nsets ? k : 0];
@@ -1335,7 +1333,7 @@ int launch_render(const BvhDesc &D, const rs_gaussians *g, const rs_rays *rays, 
     } else {
         if ((e = launch_sets(D, g, p, 1, &S, pool, Pass::AdjointTraverse, st))) return e;
     }
-    scatter_gacc(D, grads, st);
+    scatter_gacc(D, g->quat, grads, st);
     return hipGetLastError() == hipSuccess ? RS_OK : RS_ERR_HIP;
 }
 

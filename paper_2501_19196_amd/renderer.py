@@ -255,20 +255,40 @@ def read_counters(bvh: BVH):
     return dict(zip(COUNTER_NAMES, (int(x) for x in out)))
 
 
-def hit_lists(rays: Rays, params: Params, state, cap=None):
-    """Host copies of the stored hit lists of a ray state (rs_hit_lists_download):
-    dict(count, stored, extra, ids[n, cap] with -1 padding)."""
-    n = rays.n
+def _lists_out(m, cap):
+    return (np.zeros(max(m, 1), np.int32), np.zeros(max(m, 1), np.int32), np.zeros(max(m, 1), np.int32),
+            np.zeros((max(m, 1), cap), np.int32))
+
+
+def hit_lists(rays: Rays, params: Params, state, cap=None, select=None):
+    """Host copies of the stored hit lists of a ray state (rs_hit_lists_download),
+    for every ray or for the ray indices in `select`: dict(count, stored, extra,
+    ids[m, cap] with -1 padding)."""
     cap = int(cap or max(params.max_hits, 1))
-    count = np.zeros(max(n, 1), np.int32)
-    stored = np.zeros(max(n, 1), np.int32)
-    extra = np.zeros(max(n, 1), np.int32)
-    ids = np.zeros((max(n, 1), cap), np.int32)
+    sel = None if select is None else np.ascontiguousarray(select, np.int64)
+    m = rays.n if sel is None else len(sel)
+    count, stored, extra, ids = _lists_out(m, cap)
     rc, pc = rays.c(), params.c()
     p = lambda a: a.ctypes.data_as(C.c_void_p)
-    L.check(L.lib().rs_hit_lists_download(C.byref(rc), C.byref(pc), _ptr(state), p(count), p(stored), p(extra),
-                                          p(ids), cap, _stream()), "rs_hit_lists_download")
-    return dict(count=count[:n], stored=stored[:n], extra=extra[:n], ids=ids[:n])
+    L.check(L.lib().rs_hit_lists_download(C.byref(rc), C.byref(pc), _ptr(state), None if sel is None else p(sel),
+                                          m, p(count), p(stored), p(extra), p(ids), cap, _stream()),
+            "rs_hit_lists_download")
+    return dict(count=count[:m], stored=stored[:m], extra=extra[:m], ids=ids[:m])
+
+
+def mesh_hit_lists(rays: Rays, params: Params, shading, frame, ray_set, cap=None, select=None):
+    """Stored hit lists of ray set `ray_set` of a mesh frame (rs_mesh_hit_lists_download):
+    0..B path levels, B+1..2B shadow levels."""
+    cap = int(cap or max(params.max_hits, 1))
+    sel = None if select is None else np.ascontiguousarray(select, np.int64)
+    m = rays.n if sel is None else len(sel)
+    count, stored, _, ids = _lists_out(m, cap)
+    rc, pc, sc = rays.c(), params.c(), shading.c()
+    p = lambda a: a.ctypes.data_as(C.c_void_p)
+    L.check(L.lib().rs_mesh_hit_lists_download(C.byref(rc), C.byref(pc), C.byref(sc), _ptr(frame), int(ray_set),
+                                               None if sel is None else p(sel), m, p(count), p(stored), p(ids), cap,
+                                               _stream()), "rs_mesh_hit_lists_download")
+    return dict(count=count[:m], stored=stored[:m], ids=ids[:m])
 
 
 def download(bvh: BVH):
