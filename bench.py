@@ -79,6 +79,11 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-recompute", action="store_true", help="skip the re-traversing adjoint's step")
     ap.add_argument("--no-batching", action="store_true", help="skip the batched vs per-view comparison")
+    ap.add_argument("--batching-only", choices=("both", "batched", "per-view"), default=None,
+                    help="run only the batched vs per-view comparison, in one or both forms (for profiling); "
+                         "prints no JSON line")
+    ap.add_argument("--batching-workloads", default="3,5",
+                    help="workloads of the batched vs per-view comparison (3: 8-view batch, 5: mesh primaries)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-rays", type=int, default=8000)
     ap.add_argument("--parity-rays", type=int, default=2048)
@@ -116,6 +121,37 @@ def main():
     from synthetic.cameras import concat_rays
     from synthetic.scenes import jittered_target
     from paper_2501_19196_amd import renderer as R
+
+    if args.batching_only:
+        dev = torch.device("cuda:0")
+        ev = lambda: torch.cuda.Event(enable_timing=True)
+
+        def timed(fn, steps):
+            s0, s1 = ev(), ev()
+            torch.cuda.synchronize()
+            s0.record()
+            res = [fn() for _ in range(steps)]
+            s1.record()
+            torch.cuda.synchronize()
+            return s0.elapsed_time(s1) / steps, res
+
+        def graph_of(fn):
+            side = torch.cuda.Stream()
+            side.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(side):
+                fn()
+            torch.cuda.current_stream().wait_stream(side)
+            torch.cuda.synchronize()
+            gph = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gph):
+                fn()
+            torch.cuda.synchronize()
+            return gph
+
+        forms = ("batched_persistent", "per_view") if args.batching_only == "both" else \
+            (("batched_persistent",) if args.batching_only == "batched" else ("per_view",))
+        batching_comparison(R, dev, args, ev, timed, graph_of, log, forms)
+        return
 
     t0 = time.time()
     w = workload(args.workload)
@@ -544,7 +580,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def batching_comparison(R, dev, args, ev, timed, graph_of, log):
+def batching_comparison(R, dev, args, ev, timed, graph_of, log, forms=("batched_persistent", "per_view")):
     """Forward and forward+backward of the 8-view batch (300k Gaussians, 4 x
     800x800 + 4 x 400x300) and of the mesh workload's primary rays (500k
     Gaussians, 4 x 1024x768) in two forms on the same GPU: one persistent launch
@@ -557,7 +593,7 @@ def batching_comparison(R, dev, args, ev, timed, graph_of, log):
     from synthetic.cameras import concat_rays
 
     res = {}
-    for k in (3, 5):
+    for k in (int(x) for x in args.batching_workloads.split(",")):
         t0 = time.time()
         w = workload(k)
         sc = w["scene"]
@@ -614,6 +650,8 @@ def batching_comparison(R, dev, args, ev, timed, graph_of, log):
         fbb_bytes = fb_bytes + compulsory_bwd(nr, n, comp, hl > 0)
         row = dict(gaussians=n, rays=nr, views=len(views), identical_forward=same)
         for form, f_fwd, f_fb in (("batched_persistent", fwd_b, fb_b), ("per_view", fwd_v, fb_v)):
+            if form not in forms:
+                continue
             for _ in range(2):
                 f_fb()
             ga, gb = graph_of(f_fwd), graph_of(f_fb)
@@ -625,8 +663,9 @@ def batching_comparison(R, dev, args, ev, timed, graph_of, log):
                              fwd_bwd_mrays_s=round(nr / (ms_fb * 1e-3) / 1e6, 2),
                              fwd_hbm_frac=round(fb_bytes / (ms_f * 1e-3) / 1e9 / PEAK_HBM_GBS, 6),
                              fwd_bwd_hbm_frac=round(fbb_bytes / (ms_fb * 1e-3) / 1e9 / PEAK_HBM_GBS, 6))
-        row["speedup_fwd"] = round(row["per_view"]["fwd_ms"] / row["batched_persistent"]["fwd_ms"], 3)
-        row["speedup_fwd_bwd"] = round(row["per_view"]["fwd_bwd_ms"] / row["batched_persistent"]["fwd_bwd_ms"], 3)
+        if len(forms) == 2:
+            row["speedup_fwd"] = round(row["per_view"]["fwd_ms"] / row["batched_persistent"]["fwd_ms"], 3)
+            row["speedup_fwd_bwd"] = round(row["per_view"]["fwd_bwd_ms"] / row["batched_persistent"]["fwd_bwd_ms"], 3)
         row["status"] = R.read_status(bvh)
         res[name] = row
         log(f"batching {name}: {row} ({time.time() - t0:.1f}s)")
