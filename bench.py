@@ -568,7 +568,8 @@ def main():
         "work_per_ray_bwd": {k: round(v / nr, 3) for k, v in cb.items() if v},
         "hit_lists": dict(pool_slots_per_ray=base.hit_list,
                           rows_per_packet=round(cf["list_rows"] / max(cf["packets"], 1), 2),
-                          slots_used_frac=round(cf["list_rows"] * 64 / max(pool_slots, 1), 4) if lists else None,
+                          slots_per_packet=round(cf["list_slots"] / max(cf["packets"], 1), 1),
+                          slots_used_frac=round(cf["list_slots"] / max(pool_slots, 1), 4) if lists else None,
                           ray_state_bytes=R.state_bytes(nr, base),
                           pool_exhausted=bool(cb["adjoint_packets"] > 0) if lists else None),
         "autotune": tune,

@@ -69,8 +69,10 @@ enum {
                                       while their transmittance stays >= eps2 (image unchanged),
                                       and the last composited Gaussian's gradient sees them
                                       instead of the background. Needs 0 < max_hits and
-                                      hit_list > 0; a pool of max_hits + 64 slots per ray
-                                      never runs out (RS_ERR_LIST_POOL otherwise).
+                                      hit_list > 0; with full 64-ray packets a pool of
+                                      5/4 max_hits + 8 slots per ray never runs out
+                                      (RS_ERR_LIST_POOL otherwise; a packet of r rays
+                                      stores at most (r + 2) max_hits slots).
                                       Not for the mesh renders. */
 
 #define RS_BUILD_LBVH   (1u << 5)  /* rs_build_bvh: link the Morton-sorted leaves as a binary radix
@@ -121,8 +123,9 @@ typedef struct {
  * hit_list: store-or-recompute choice of the adjoint (0..4096; 0 = recompute):
  * with C > 0 the forward also records the ids of the Gaussians each ray
  * composites, in a pool of C 4-byte slots per ray on average inside the ray
- * state (a packet of 64 rays takes one row of 64 slots per compositing step of
- * its wavefront, from chunks of 8 rows), and the adjoint replays those lists
+ * state (per compositing step of its wavefront a packet of 64 rays stores one
+ * row: the ids of the lanes that took a hit at that step and their 64-bit lane
+ * mask, in chunks of 512 slots), and the adjoint replays those lists
  * instead of traversing the BVH again. The rays of a packet that finds the pool
  * exhausted are traversed again by the adjoint. The gradients are the same (up to
  * float atomic order). The mesh renders keep one pool for all their ray sets in
@@ -219,8 +222,9 @@ int rs_read_status(const rs_bvh *bvh, void *stream);
  * collected by the paper variant), traversal adjoint: hits differentiated, [7]
  * lane child-box overlaps, [8] traversal adjoint: per-wave gradient groups
  * (distinct Gaussians per step), stored-list adjoint: [9] ray packets, [10]
- * differentiated hits, [11] gradient groups; [12] stored-list rows appended
- * by the forward, [13] traversal adjoint packets, [14], [15] unused.
+ * differentiated hits, [11] gradient groups; [12] stored-list rows the
+ * forward stored, [13] traversal adjoint packets, [14] stored-list slots the
+ * forward stored (ids and lane masks), [15] unused.
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 

@@ -2,6 +2,7 @@
 // the build and render launchers.
 #include <string.h>
 
+#include <algorithm>
 #include <unordered_map>
 #include <vector>
 
@@ -510,15 +511,17 @@ static int lists_download(const rs_rays *rays, int tile_shift, const int4 *dev_l
     unsigned long long taken = 0;
     if (hipMemcpy(&taken, P.hdr, 8, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
     const int64_t used = int64_t(taken < (unsigned long long)P.chunks ? taken : (unsigned long long)P.chunks);
-    std::vector<int32_t> prev(size_t(used > 0 ? used : 1));
-    std::vector<uint32_t> slots(size_t(used > 0 ? used : 1) * kListRows * kWave);
+    std::vector<int32_t> prev(size_t(used > 0 ? used : 1)), fill(size_t(used > 0 ? used : 1));
+    std::vector<uint32_t> slots(size_t(used > 0 ? used : 1) * kChunkSlots);
     if (used > 0) {
-        if (hipMemcpy(prev.data(), P.prev, size_t(used) * 4, hipMemcpyDeviceToHost) != hipSuccess) return RS_ERR_HIP;
-        if (hipMemcpy(slots.data(), P.slots, size_t(used) * kListRows * kWave * 4, hipMemcpyDeviceToHost) !=
-            hipSuccess)
+        if (hipMemcpy(prev.data(), P.prev, size_t(used) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(fill.data(), P.fill, size_t(used) * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            hipMemcpy(slots.data(), P.slots, size_t(used) * kChunkSlots * 4, hipMemcpyDeviceToHost) != hipSuccess)
             return RS_ERR_HIP;
     }
-    std::unordered_map<int32_t, std::vector<int32_t>> chains;  // a packet's chunks, first to last
+    // a packet's rows, first to last: (first slot, lane mask); a chunk's rows are found
+    // from its fill backwards, each row ending with its mask
+    std::unordered_map<int32_t, std::vector<std::pair<int64_t, uint64_t>>> chains;
     for (int64_t i = 0; i < m; ++i) {
         const int64_t r = sel ? sel[i] : i;
         const int4 L = li[size_t(r)];
@@ -528,18 +531,28 @@ static int lists_download(const rs_rays *rays, int tile_shift, const int4 *dev_l
         if (L.w > 0 && L.z >= 0 && L.z < used) {
             auto it = chains.find(L.z);
             if (it == chains.end()) {
-                std::vector<int32_t> ch;
-                for (int32_t c = L.z; c >= 0 && c < used && int64_t(ch.size()) <= used; c = prev[size_t(c)])
-                    ch.push_back(c);
-                std::vector<int32_t> fw(ch.rbegin(), ch.rend());
-                it = chains.emplace(L.z, std::move(fw)).first;
+                std::vector<std::pair<int64_t, uint64_t>> rows;  // last to first
+                int64_t hops = 0;
+                for (int32_t c = L.z; c >= 0 && c < used && hops <= used; c = prev[size_t(c)], ++hops) {
+                    int32_t end = fill[size_t(c)];
+                    if (end < 0 || end > kChunkSlots) break;
+                    while (end >= 2) {
+                        const size_t at = size_t(c) * kChunkSlots + size_t(end);
+                        const uint64_t mask = uint64_t(slots[at - 2]) | (uint64_t(slots[at - 1]) << 32);
+                        const int32_t k = __builtin_popcountll(mask);
+                        if (k + 2 > end) break;
+                        end -= k + 2;
+                        rows.emplace_back(int64_t(c) * kChunkSlots + end, mask);
+                    }
+                }
+                std::reverse(rows.begin(), rows.end());
+                it = chains.emplace(L.z, std::move(rows)).first;
             }
-            const std::vector<int32_t> &ch = it->second;
             const int lane = ray_lane(rays, tile_shift, r);
-            for (int32_t row = 0; row < L.w && size_t(row / kListRows) < ch.size(); ++row) {
-                const uint32_t v =
-                    slots[(size_t(ch[size_t(row / kListRows)]) * kListRows + size_t(row % kListRows)) * kWave + lane];
-                if (v == kListIdle) continue;
+            for (const auto &row : it->second) {
+                if (!((row.second >> lane) & 1ull)) continue;
+                const uint64_t below = lane ? row.second & ((1ull << lane) - 1ull) : 0ull;
+                const uint32_t v = slots[size_t(row.first) + size_t(__builtin_popcountll(below))];
                 if (v & kListSecond) ++x;
                 if (ids && w < cap) ids[i * int64_t(cap) + w] = int32_t(v & ~kListSecond);
                 ++w;

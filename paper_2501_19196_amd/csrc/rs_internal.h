@@ -177,8 +177,8 @@ __device__ inline float ordered_to_float(uint32_t u)
 //            T restarts the recursion where it would divide 0 by 0 or lose its
 //            digits in the subnormals.
 //   list[n]  int4 (only with stored hit lists): composited hits, how many of
-//            them the pool holds, the ray's packet's last pool chunk and its
-//            stored row count.
+//            them the pool holds, the ray's packet's last pool chunk and the
+//            packet's stored row count.
 struct SetState {
     float4 *fin;
     uint4 *last;
@@ -186,38 +186,42 @@ struct SetState {
 };
 
 // Stored hit lists: one pool shared by every packet of a launch. A packet's
-// wavefront appends one row of 64 slots (one per lane: the Gaussian index it
-// composited at that step, the index | kListSecond for a hit it only collected
-// in the paper variant's second phase, kListIdle otherwise) per compositing
-// step; rows live in chunks of kListRows, linked backwards per packet. The
-// pool header holds the chunk counter (64-bit) and a flag set when a packet
-// found the pool exhausted (its later rows are not stored).
-constexpr int kListRows = 8;
+// wavefront appends one row per compositing step: the entries of the lanes that
+// consumed a hit at that step, in lane order (the Gaussian index it composited,
+// or the index | kListSecond for a hit it only collected in the paper variant's
+// second phase), then the 64-bit mask of those lanes as two words. Rows are
+// packed into chunks of kChunkSlots 4-byte slots (a row never straddles two
+// chunks), linked backwards per packet; fill[c] is the number of slots chunk c
+// holds. The pool header holds the chunk counter (64-bit) and a flag set when a
+// packet found the pool exhausted (its later rows are not stored).
+constexpr int kChunkSlots = 512;
 constexpr uint32_t kListIdle = 0xffffffffu;
 constexpr uint32_t kListSecond = 0x80000000u;
 struct ListPool {
     unsigned long long *hdr;  // [0] chunks taken, [1] exhausted flag
     int32_t *prev;            // [chunks] previous chunk of the same packet (-1: first)
-    uint32_t *slots;          // [chunks][kListRows][64]
+    int32_t *fill;            // [chunks] slots used
+    uint32_t *slots;          // [chunks][kChunkSlots]
     int64_t chunks;
 };
 inline int64_t list_chunks(int64_t slots_wanted)
 {
-    return (slots_wanted + int64_t(kListRows) * 64 - 1) / (int64_t(kListRows) * 64);
+    return (slots_wanted + kChunkSlots - 1) / kChunkSlots;
 }
-// bytes of a pool of `chunks` chunks (header, links, slots), 256-byte aligned
+// bytes of a pool of `chunks` chunks (header, links, fills, slots), 256-byte aligned
 inline size_t list_pool_bytes(int64_t chunks)
 {
     if (chunks <= 0) return 0;
-    return 256 + align256(size_t(chunks) * 4) + size_t(chunks) * kListRows * 64 * 4;
+    return 256 + 2 * align256(size_t(chunks) * 4) + size_t(chunks) * kChunkSlots * 4;
 }
 inline ListPool list_pool_at(char *base, int64_t chunks)
 {
-    ListPool P{nullptr, nullptr, nullptr, 0};
+    ListPool P{nullptr, nullptr, nullptr, nullptr, 0};
     if (!base || chunks <= 0) return P;
     P.hdr = reinterpret_cast<unsigned long long *>(base);
     P.prev = reinterpret_cast<int32_t *>(base + 256);
-    P.slots = reinterpret_cast<uint32_t *>(base + 256 + align256(size_t(chunks) * 4));
+    P.fill = reinterpret_cast<int32_t *>(base + 256 + align256(size_t(chunks) * 4));
+    P.slots = reinterpret_cast<uint32_t *>(base + 256 + 2 * align256(size_t(chunks) * 4));
     P.chunks = chunks;
     return P;
 }

@@ -511,21 +511,28 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
 struct ListCursor {
     int32_t rows;   // rows stored
     int32_t chunk;  // current chunk (-1: none yet)
+    int32_t fill;   // slots used in the current chunk
+    int32_t slots;  // slots stored (rows and masks)
     bool ok;        // false once the pool was found exhausted
 };
 
-// Appends one row (one value per lane; called from wave-uniform control flow): a
-// new chunk, linked to the packet's previous one, is taken from the pool every
-// kListRows rows. Once the pool is exhausted the packet stores nothing more (the
-// adjoint then traverses for its rays, or, for the paper variant, the sticky
-// status reports it).
+// Appends one row (called from wave-uniform control flow): the entries of the lanes
+// whose `entry` is not kListIdle, in lane order, then their lane mask as two words.
+// A row that does not fit the current chunk starts a new one, taken from the pool
+// and linked to the packet's previous chunk. Once the pool is exhausted the packet
+// stores nothing more (the adjoint then traverses for its rays, or, for the paper
+// variant, the sticky status reports it).
 __device__ inline void list_append(const ListPool &pool, ListCursor &L, uint32_t entry, int lane, int32_t &stored,
                                    bool paper, int32_t *status)
 {
     if (!L.ok) return;
-    if ((L.rows & (kListRows - 1)) == 0) {
+    const uint64_t m = wave_ballot(entry != kListIdle);
+    if (m == 0) return;
+    const int32_t need = __popcll(m) + 2;
+    if (L.chunk < 0 || L.fill + need > kChunkSlots) {
         int32_t c = 0;
         if (lane == 0) {
+            if (L.chunk >= 0) pool.fill[L.chunk] = L.fill;
             const unsigned long long k = atomicAdd(pool.hdr, 1ull);
             c = k < (unsigned long long)pool.chunks ? int32_t(k) : -1;
         }
@@ -540,10 +547,27 @@ __device__ inline void list_append(const ListPool &pool, ListCursor &L, uint32_t
         }
         if (lane == 0) pool.prev[c] = L.chunk;
         L.chunk = c;
+        L.fill = 0;
     }
-    pool.slots[(int64_t(L.chunk) * kListRows + (L.rows & (kListRows - 1))) * kWave + lane] = entry;
-    if (entry < kListSecond) ++stored;
+    uint32_t *row = pool.slots + int64_t(L.chunk) * kChunkSlots + L.fill;
+    if (entry != kListIdle) {
+        const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+        row[below] = entry;
+        if (entry < kListSecond) ++stored;
+    }
+    if (lane == 0) {
+        row[need - 2] = uint32_t(m);
+        row[need - 1] = uint32_t(m >> 32);
+    }
+    L.fill += need;
+    L.slots += need;
     ++L.rows;
+}
+
+// Records the fill of the packet's last chunk (after its last row).
+__device__ inline void list_close(const ListPool &pool, const ListCursor &L, int lane)
+{
+    if (L.ok && L.chunk >= 0 && lane == 0) pool.fill[L.chunk] = L.fill;
 }
 
 // min of two floats that are never NaN-signalling, as the bare instruction
@@ -698,7 +722,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
     int qi = 0;
     // work counters (wave-uniform, scalar registers; only in the COUNT variants)
     uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
-             c_rows = 0;
+             c_rows = 0, c_slots = 0;
     for (;;) {
         const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
@@ -723,7 +747,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         int32_t z = -1;
         // stored hit lists: the packet's row cursor; per lane the composited ids stored
         const bool lists = P.lists && S.list != nullptr;
-        ListCursor LC{0, -1, true};
+        ListCursor LC{0, -1, 0, 0, true};
         int32_t stored = 0;
         // RS_PAPER_GRADIENT forward: after an eps1 stop the lane keeps consuming hits without
         // compositing them, recording their ids while T2 (their transmittance) stays >= eps2
@@ -830,15 +854,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                             live = false;
                     }
                 }
-                if (lists) {
-                    if (COUNT) ++c_rows;
-                    list_append(ptr.pool, LC, entry, lane, stored, paper, ptr.status);
-                }
+                if (lists) list_append(ptr.pool, LC, entry, lane, stored, paper, ptr.status);
             }
             // a lane whose buffer did not fill has consumed all its hits
             if (live && round_last == kNoHit) live = false;
         }
 
+        if (lists) {
+            list_close(ptr.pool, LC, lane);
+            if (COUNT) {
+                c_rows += uint64_t(LC.rows);
+                c_slots += uint64_t(LC.slots);
+            }
+        }
         if (valid) {
             const float orr = __builtin_fmaf(A.T, bgr, A.Cr), og = __builtin_fmaf(A.T, bgg, A.Cg),
                         ob = __builtin_fmaf(A.T, bgb, A.Cb);
@@ -864,6 +892,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         atomicAdd(ptr.counters + 6, (unsigned long long)c_lcomp);
         atomicAdd(ptr.counters + 7, (unsigned long long)c_lchild);
         atomicAdd(ptr.counters + 12, (unsigned long long)c_rows);
+        atomicAdd(ptr.counters + 14, (unsigned long long)c_slots);
     }
 }
 
@@ -1049,21 +1078,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
             B = back_init(S.fin[LR.id], S.last[LR.id], LR.bgr, LR.bgg, LR.bgb);
             live = li.x > 0 && li.y == li.x && P.n_gauss > 0 && !(Gd.gr == 0.0f && Gd.gg == 0.0f && Gd.gb == 0.0f);
         }
-        // the packet's rows (lane 0 always holds one of the packet's rays)
-        const int32_t rows = __builtin_amdgcn_readfirstlane(li.w);
+        // the packet's last chunk (lane 0 always holds one of the packet's rays)
         int32_t chunk = __builtin_amdgcn_readfirstlane(li.z);
-        if (!wave_ballot(live)) continue;
-        // the entry of the next row (back to front) is loaded one row ahead
-        uint32_t e_next = live && rows > 0
-                              ? pool.slots[(int64_t(chunk) * kListRows + ((rows - 1) & (kListRows - 1))) * kWave + lane]
-                              : kListIdle;
-        for (int32_t row = rows - 1; row >= 0; --row) {
-            const uint32_t e = e_next;
-            if (row > 0) {
-                if ((row & (kListRows - 1)) == 0) chunk = pool.prev[chunk];
-                e_next = live ? pool.slots[(int64_t(chunk) * kListRows + ((row - 1) & (kListRows - 1))) * kWave + lane]
-                              : kListIdle;
+        if (!wave_ballot(live) || chunk < 0) continue;
+        // rows are walked from the last to the first: a row ends with its lane mask, so the
+        // mask at the row's end gives its start, which is the previous row's end
+        int32_t end = pool.fill[chunk];
+        for (;;) {
+            while (end == 0 && chunk >= 0) {
+                chunk = pool.prev[chunk];
+                end = chunk >= 0 ? pool.fill[chunk] : 0;
             }
+            if (chunk < 0) break;
+            const uint32_t *row_end = pool.slots + int64_t(chunk) * kChunkSlots + end;
+            const uint64_t m = uint64_t(row_end[-2]) | (uint64_t(row_end[-1]) << 32);
+            const int32_t k = __popcll(m);
+            end -= k + 2;
+            const uint32_t *row = row_end - 2 - k;
+            const bool mine = ((m >> lane) & 1ull) != 0;
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+            const uint32_t e = live && mine ? row[below] : kListIdle;
             const bool act = e != kListIdle;
             if (!wave_ballot(act)) continue;
             const bool comp = act && e < kListSecond;

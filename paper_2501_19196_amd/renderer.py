@@ -245,7 +245,7 @@ def raise_on_status(bvh: BVH, what):
 
 COUNTER_NAMES = ("packets", "node_visits", "leaf_visits", "rounds", "lane_leaf_tests", "lane_hits_buffered",
                  "lane_composited", "lane_child_overlaps", "grad_groups", "list_packets", "list_composited",
-                 "list_grad_groups", "list_rows", "adjoint_packets", "c14", "c15")
+                 "list_grad_groups", "list_rows", "adjoint_packets", "list_slots", "c15")
 
 
 def read_counters(bvh: BVH):

@@ -77,13 +77,14 @@ def test_defaults_and_strings(L):
     lib.rs_default_params(C.byref(q))
     q.hit_list = 8
     # then the list bookkeeping (16 bytes per ray) and the pool: a 256-byte header, the
-    # chunk links and whole chunks of 8 rows x 64 slots x 4 bytes (80 slots -> one chunk)
-    assert lib.rs_ray_state_bytes(10, C.byref(q)) == 512 + 256 + 256 + 256 + 8 * 64 * 4
+    # chunk links, the chunk fills and whole chunks of 512 slots x 4 bytes (80 slots -> one
+    # chunk)
+    assert lib.rs_ray_state_bytes(10, C.byref(q)) == 512 + 256 + 256 + 256 + 256 + 512 * 4
     q.hit_list = 100
     n = 100000
     chunks = (n * 100 + 511) // 512
     head = (n * 16 + 255) // 256 * 256
-    assert lib.rs_ray_state_bytes(n, C.byref(q)) == 3 * head + 256 + (chunks * 4 + 255) // 256 * 256 + chunks * 2048
+    assert lib.rs_ray_state_bytes(n, C.byref(q)) == 3 * head + 256 + 2 * ((chunks * 4 + 255) // 256 * 256) + chunks * 2048
     a, b = lib.rs_bvh_workspace_bytes(1000), lib.rs_bvh_workspace_bytes(100000)
     assert 0 < a < b and b % 256 == 0
 

@@ -365,6 +365,8 @@ def test_stored_hit_lists_oracle_parity_and_counters():
     assert cb["lane_composited"] == cf["lane_composited"]  # no traversal adjoint ran
     assert cb["adjoint_packets"] == 0
     assert cf["list_rows"] >= cf["lane_composited"] / 64
+    # dense rows: one id per composited hit plus a two-word lane mask per row
+    assert cf["list_slots"] == cf["lane_composited"] + 2 * cf["list_rows"]
 
 
 # ------------------------------------------- the paper's gradient variant (second threshold)
