@@ -220,11 +220,11 @@ int rs_read_status(const rs_bvh *bvh, void *stream);
  * traversal rounds (all per wavefront), [4] lane leaf tests on live rays, [5]
  * hits entering a lane's buffer, [6] forward: hits consumed (composited, or
  * collected by the paper variant), traversal adjoint: hits differentiated, [7]
- * lane child-box overlaps, [8] traversal adjoint: per-wave gradient groups
- * (distinct Gaussians per step), stored-list adjoint: [9] ray packets, [10]
- * differentiated hits, [11] gradient groups; [12] stored-list rows the
- * forward stored, [13] traversal adjoint packets, [14] stored-list slots the
- * forward stored (ids and lane masks), [15] unused.
+ * lane child-box overlaps, [8] traversal adjoint: accumulator lines flushed
+ * from its LDS tables, stored-list adjoint: [9] ray packets, [10]
+ * differentiated hits, [11] gradient groups (distinct Gaussians per step);
+ * [12] stored-list rows the forward stored, [13] traversal adjoint packets,
+ * [14] stored-list slots the forward stored (ids and lane masks), [15] unused.
  * Instrumentation for tuning and roofline accounting; not part of the method. */
 int rs_read_counters(const rs_bvh *bvh, uint64_t *out, void *stream);
 

@@ -445,13 +445,99 @@ __device__ inline void back_over(Back &B, float al, float cr, float cg, float cb
     B.Sb = __builtin_fmaf(al, cb - B.Sb, B.Sb);
 }
 
+// Per-wave gradient accumulation in LDS (the traversal adjoint): a table of Gaussian slots,
+// each holding the 13 partial sums of one Gaussian, found by hashing its index with linear
+// probing over kAccProbes slots. Every hit adds its values into its Gaussian's slot with LDS
+// atomics; a slot's sums reach the global accumulators (one 64-byte line per Gaussian) only
+// when the table is flushed: when some lane finds no slot in its probe window, and at the end
+// of the kernel. The hits of one Gaussian on the rays of a packet, over every compositing
+// step, so cost one line of global atomics per flush instead of one per step. The workgroup
+// is one wave.
+constexpr int kAccSlots = 128;
+constexpr int kAccProbes = 8;
+constexpr int kAccVals = 13;
+struct AccTable {
+    int32_t tag[kAccSlots];           // Gaussian index, -1: free
+    int32_t list[kAccSlots];          // occupied slots, compacted by a flush
+    float acc[kAccSlots * kAccVals];  // partial sums (odd stride: distinct slots, distinct banks)
+};
+
+__device__ inline AccTable &acc_table()
+{
+    __shared__ AccTable T;
+    return T;
+}
+
+__device__ inline void acc_clear(AccTable &T, int lane)
+{
+    for (int s = lane; s < kAccSlots; s += kWave) T.tag[s] = -1;
+    for (int s = lane; s < kAccSlots * kAccVals; s += kWave) T.acc[s] = 0.0f;
+    __syncthreads();
+}
+
+__device__ inline uint32_t acc_home(uint32_t gid)
+{
+    return uint32_t((uint64_t(gid * 2654435761u) * uint64_t(kAccSlots)) >> 32);
+}
+
+// Adds every occupied slot's sums to the global accumulators (16-lane segments, one slot
+// each, lane v of a segment adding value v) and frees the table.
+template <bool COUNT>
+__device__ inline void acc_flush(AccTable &T, float *gacc, int lane, uint64_t &c_group)
+{
+    __syncthreads();
+    int32_t cnt = 0;
+    for (int base = 0; base < kAccSlots; base += kWave) {
+        const int s = base + lane;
+        const bool occ = s < kAccSlots && T.tag[s] != -1;
+        const uint64_t m = wave_ballot(occ);
+        if (occ) T.list[cnt + int32_t(__builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u)))] = s;
+        cnt += __popcll(m);
+    }
+    __syncthreads();
+    const int v = lane & 15, q = lane >> 4;
+    for (int i = 0; i < cnt; i += 4) {
+        const int k = i + q;
+        if (k < cnt && v < kAccVals) {
+            const int s = T.list[k];
+            const uint32_t g = uint32_t(T.tag[s]);
+            float *a = T.acc + s * kAccVals + v;
+            unsafeAtomicAdd(gacc + 16 * int64_t(g) + v, *a);
+            *a = 0.0f;
+        }
+    }
+    if (COUNT) c_group += uint64_t(cnt);
+    __syncthreads();
+    for (int s = lane; s < kAccSlots; s += kWave) T.tag[s] = -1;
+    __syncthreads();
+}
+
+// One step of the pairwise sum: lanes paired by the DPP pattern CTRL (an involution) that
+// hold the same Gaussian are merged into the `keep` lane of the pair. Called with every lane
+// of the wave active.
+template <int CTRL>
+__device__ inline void acc_pair(bool &act, uint32_t gid, GradOut &G, bool keep)
+{
+    const int32_t pg = __builtin_amdgcn_mov_dpp(int32_t(gid), CTRL, 0xF, 0xF, false);
+    const int32_t pa = __builtin_amdgcn_mov_dpp(act ? 1 : 0, CTRL, 0xF, 0xF, false);
+    const bool m = act && pa != 0 && pg == int32_t(gid);
+#pragma unroll
+    for (int v = 0; v < kAccVals; ++v) {
+        const float pv = __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(G.v[v]), CTRL, 0xF, 0xF, false));
+        G.v[v] = (m && keep) ? G.v[v] + pv : G.v[v];
+    }
+    act = act && !(m && !keep);
+}
+
 // Adjoint of one composited hit (App. A.3-A.6) and its wave aggregation.
 //   dL/dalpha_k = T_k <g, c_k - S_{k+1}>,  dL/dc_k = alpha_k T_k g,
-// then alpha's chain rule (grad_hit). The active lanes' contributions are summed
-// per distinct Gaussian through LDS and one 14-lane segment of an atomic
-// instruction adds each Gaussian's totals to its 64-byte accumulator line (four
-// Gaussians per instruction).
-template <bool COUNT>
+// then alpha's chain rule (grad_hit). TABLE: the contributions go into the wave's LDS table
+// (the traversal adjoint, whose long traversal hides the LDS atomics). Otherwise (the stored-
+// list adjoint, where the table's same-address LDS atomics would be the bottleneck) the active
+// lanes' contributions are summed per distinct Gaussian of this step through LDS, and one
+// 13-lane segment of an atomic instruction adds each Gaussian's totals to its 64-byte
+// accumulator line (four Gaussians per instruction).
+template <bool COUNT, bool TABLE>
 __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, const HitData &H, float Tk,
                                    const Back &B, const LaneGrad &Gd, bool zc, float *gacc, int lane, uint64_t &c_group)
 {
@@ -466,41 +552,79 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
         G.v[11] = zc ? 0.0f : Gd.gg * wgt;
         G.v[12] = zc ? 0.0f : Gd.gb * wgt;
     }
-    // Lanes holding the same Gaussian form a group; groups are numbered in order and each
-    // group's lanes store their 13 values in consecutive LDS rows. Then 16-lane segments sum
-    // one group's rows each, so one atomic instruction adds the totals of four Gaussians (one
-    // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
-    // operations complete in order.
-    __shared__ float rows[kWave * 16];
-    __shared__ int4 groups[kWave];  // Gaussian index, first row, rows
-    const uint64_t lane_bit = 1ull << lane;
-    uint64_t todo = act_mask;
-    int ng = 0, pos = 0, mypos = 0;
-    while (todo) {
-        const int leader = __builtin_ctzll(todo);
-        const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
-        const uint64_t same = wave_ballot(act && gid == lg);
-        todo &= ~same;
-        if (COUNT) ++c_group;
-        const int m = __popcll(same);
-        mypos = (same & lane_bit) ? pos + __popcll(same & (lane_bit - 1)) : mypos;
-        if (lane == leader) groups[ng] = make_int4(int32_t(lg), pos, m, 0);
-        ++ng;
-        pos += m;
-    }
-    if (act) {
-        float *r = rows + 16 * mypos;
+    if constexpr (TABLE) {
+        (void)act_mask;
+        // Lanes of one 16-lane row holding the same Gaussian are first summed pairwise (lane^1,
+        // lane^2, then mirrored halves and rows: neighbouring pixels of the packet tile), so
+        // fewer LDS atomics meet at one address.
+        acc_pair<0xB1>(act, gid, G, (lane & 1) == 0);   // quad_perm [1,0,3,2]
+        acc_pair<0x4E>(act, gid, G, (lane & 2) == 0);   // quad_perm [2,3,0,1]
+        acc_pair<0x141>(act, gid, G, (lane & 7) < 4);   // row_half_mirror
+        acc_pair<0x140>(act, gid, G, (lane & 15) < 8);  // row_mirror
+        AccTable &T = acc_table();
+        const uint32_t home = acc_home(gid);
+        bool pend = act;
+        for (;;) {
+            int32_t slot = -1;
+            if (pend) {
+                uint32_t h = home;
+                for (int p = 0; p < kAccProbes; ++p) {
+                    const int32_t old = atomicCAS(&T.tag[h], -1, int32_t(gid));
+                    if (old == -1 || old == int32_t(gid)) {
+                        slot = int32_t(h);
+                        break;
+                    }
+                    h = h + 1 == uint32_t(kAccSlots) ? 0u : h + 1;
+                }
+            }
+            if (slot >= 0) {
+                float *a = T.acc + slot * kAccVals;
 #pragma unroll
-        for (int v = 0; v < 13; ++v) r[v] = G.v[v];
-    }
-    const int v = lane & 15;
-    for (int b = 0; b < ng; b += 4) {
-        const int gi = b + (lane >> 4);
-        if (gi < ng && v < 13) {
-            const int4 gd = groups[gi];
-            float t = rows[16 * gd.y + v];
-            for (int j = 1; j < gd.z; ++j) t += rows[16 * (gd.y + j) + v];
-            unsafeAtomicAdd(gacc + 16 * int64_t(uint32_t(gd.x)) + v, t);
+                for (int v = 0; v < kAccVals; ++v)
+                    __hip_atomic_fetch_add(a + v, G.v[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                pend = false;
+            }
+            // lanes left without a slot: flush the table and probe again from their home slots
+            if (!wave_ballot(pend)) break;
+            acc_flush<COUNT>(T, gacc, lane, c_group);
+        }
+    } else {
+        // Lanes holding the same Gaussian form a group; groups are numbered in order and each
+        // group's lanes store their 13 values in consecutive LDS rows. Then 16-lane segments sum
+        // one group's rows each, so one atomic instruction adds the totals of four Gaussians (one
+        // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
+        // operations complete in order.
+        __shared__ float rows[kWave * 16];
+        __shared__ int4 groups[kWave];  // Gaussian index, first row, rows
+        const uint64_t lane_bit = 1ull << lane;
+        uint64_t todo = act_mask;
+        int ng = 0, pos = 0, mypos = 0;
+        while (todo) {
+            const int leader = __builtin_ctzll(todo);
+            const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
+            const uint64_t same = wave_ballot(act && gid == lg);
+            todo &= ~same;
+            if (COUNT) ++c_group;
+            const int m = __popcll(same);
+            mypos = (same & lane_bit) ? pos + __popcll(same & (lane_bit - 1)) : mypos;
+            if (lane == leader) groups[ng] = make_int4(int32_t(lg), pos, m, 0);
+            ++ng;
+            pos += m;
+        }
+        if (act) {
+            float *r = rows + 16 * mypos;
+#pragma unroll
+            for (int v = 0; v < 13; ++v) r[v] = G.v[v];
+        }
+        const int v = lane & 15;
+        for (int b = 0; b < ng; b += 4) {
+            const int gi = b + (lane >> 4);
+            if (gi < ng && v < 13) {
+                const int4 gd = groups[gi];
+                float t = rows[16 * gd.y + v];
+                for (int j = 1; j < gd.z; ++j) t += rows[16 * (gd.y + j) + v];
+                unsafeAtomicAdd(gacc + 16 * int64_t(uint32_t(gd.x)) + v, t);
+            }
         }
     }
 }
@@ -918,6 +1042,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
     int qi = 0;
     uint64_t c_pkt = 0, c_node = 0, c_leaf = 0, c_round = 0, c_lleaf = 0, c_lbuf = 0, c_lcomp = 0, c_lchild = 0,
              c_group = 0;
+    acc_clear(acc_table(), lane);
     for (;;) {
         const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
@@ -1007,7 +1132,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 HitData H;
                 recompute_hit(act, gid, ray, records, inv, ptr.rgb, zc, P.Q, H);
                 const float Tk = back_T(B, H.al);
-                adjoint_hit<COUNT>(act, act_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
+                adjoint_hit<COUNT, true>(act, act_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
                 if (act) {
                     back_over(B, H.al, H.cr, H.cg, H.cb);
                     B.T = Tk;
@@ -1023,6 +1148,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             }
         }
     }
+    acc_flush<COUNT>(acc_table(), ptr.gacc, lane, c_group);
     if (COUNT && lane == 0 && c_pkt > 0) {
         atomicAdd(ptr.counters + 1, (unsigned long long)c_node);
         atomicAdd(ptr.counters + 2, (unsigned long long)c_leaf);
@@ -1108,7 +1234,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
             const uint64_t comp_mask = wave_ballot(comp);
             if (COUNT) c_lcomp += __popcll(comp_mask);
             if (comp_mask)
-                adjoint_hit<COUNT>(comp, comp_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
+                adjoint_hit<COUNT, false>(comp, comp_mask, gid, H, Tk, B, Gd, zc, ptr.gacc, lane, c_group);
             if (act) back_over(B, H.al, H.cr, H.cg, H.cb);
             if (comp) {
                 B.T = Tk;
