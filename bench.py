@@ -571,6 +571,7 @@ def main():
                           slots_per_packet=round(cf["list_slots"] / max(cf["packets"], 1), 1),
                           slots_used_frac=round(cf["list_slots"] / max(pool_slots, 1), 4) if lists else None,
                           ray_state_bytes=R.state_bytes(nr, base),
+                          mesh_frame_bytes=(frame_for(base).numel() if mesh_np is not None else None),
                           pool_exhausted=bool(cb["adjoint_packets"] > 0) if lists else None),
         "autotune": tune,
         "batching": batching,
