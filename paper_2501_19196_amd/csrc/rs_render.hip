@@ -589,28 +589,37 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
             acc_flush<COUNT>(T, gacc, lane, c_group);
         }
     } else {
-        // Lanes holding the same Gaussian form a group; groups are numbered in order and each
-        // group's lanes store their 13 values in consecutive LDS rows. Then 16-lane segments sum
-        // one group's rows each, so one atomic instruction adds the totals of four Gaussians (one
+        // Lanes holding the same Gaussian form a group; groups are numbered in order of their
+        // lowest lane and each group's lanes store their 13 values in consecutive LDS rows. The
+        // scalar loop keeps only masks and counts in scalar registers; a lane records its row
+        // and group, and after the loop each group's lowest lane writes the group's (Gaussian,
+        // first row), the next group's first row closing it. Then 16-lane segments sum one
+        // group's rows each, so one atomic instruction adds the totals of four Gaussians (one
         // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
         // operations complete in order.
         __shared__ float rows[kWave * 16];
-        __shared__ int4 groups[kWave];  // Gaussian index, first row, rows
-        const uint64_t lane_bit = 1ull << lane;
-        uint64_t todo = act_mask;
-        int ng = 0, pos = 0, mypos = 0;
+        __shared__ int2 groups[kWave + 1];  // Gaussian index, first row
+        uint64_t todo = act_mask, leaders = 0;
+        bool pend = act;  // not yet in a group (a lane mask, like todo)
+        int32_t ng = 0, pos = 0, mypos = 0, mygrp = 0;
         while (todo) {
             const int leader = __builtin_ctzll(todo);
             const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
-            const uint64_t same = wave_ballot(act && gid == lg);
+            const bool mine = pend && gid == lg;
+            const uint64_t same = wave_ballot(gid == lg) & todo;  // the lanes of mine, as a mask
             todo &= ~same;
+            pend = pend && !mine;
+            leaders |= 1ull << leader;
             if (COUNT) ++c_group;
-            const int m = __popcll(same);
-            mypos = (same & lane_bit) ? pos + __popcll(same & (lane_bit - 1)) : mypos;
-            if (lane == leader) groups[ng] = make_int4(int32_t(lg), pos, m, 0);
+            const int32_t at = int32_t(
+                __builtin_amdgcn_mbcnt_hi(uint32_t(same >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(same), uint32_t(pos))));
+            mypos = mine ? at : mypos;
+            mygrp = mine ? ng : mygrp;
             ++ng;
-            pos += m;
+            pos += __popcll(same);
         }
+        if ((leaders >> lane) & 1ull) groups[mygrp] = make_int2(int32_t(gid), mypos);
+        if (lane == 0) groups[ng] = make_int2(0, pos);
         if (act) {
             float *r = rows + 16 * mypos;
 #pragma unroll
@@ -620,9 +629,10 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
         for (int b = 0; b < ng; b += 4) {
             const int gi = b + (lane >> 4);
             if (gi < ng && v < 13) {
-                const int4 gd = groups[gi];
+                const int2 gd = groups[gi];
+                const int32_t end = groups[gi + 1].y;
                 float t = rows[16 * gd.y + v];
-                for (int j = 1; j < gd.z; ++j) t += rows[16 * (gd.y + j) + v];
+                for (int j = gd.y + 1; j < end; ++j) t += rows[16 * j + v];
                 unsafeAtomicAdd(gacc + 16 * int64_t(uint32_t(gd.x)) + v, t);
             }
         }
