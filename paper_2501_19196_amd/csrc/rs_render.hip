@@ -1185,6 +1185,32 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 #ifndef RS_LIST_WAVES
 #define RS_LIST_WAVES 6
 #endif
+// Row cursor of the list adjoint (wave-uniform): `start` is where the row read last began,
+// so the next row (back to front) ends there, or at the fill of an earlier chunk.
+__device__ inline void row_seek(const int32_t *__restrict__ prev, const int32_t *__restrict__ fill, int32_t &chunk,
+                                int32_t &start)
+{
+    while (start == 0 && chunk >= 0) {
+        chunk = prev[chunk];
+        start = chunk >= 0 ? fill[chunk] : 0;
+    }
+}
+
+// Reads the row ending at `start` of `chunk` (its lane mask), moves `start` to the row's first
+// slot, and returns this lane's entry (kListIdle for a lane without one, or not live).
+__device__ inline uint32_t row_entry(const uint32_t *__restrict__ slots, int32_t chunk, int32_t &start, bool live,
+                                     int lane)
+{
+    const uint32_t *row_end = slots + int64_t(chunk) * kChunkSlots + start;
+    const uint64_t m = uint64_t(row_end[-2]) | (uint64_t(row_end[-1]) << 32);
+    const int32_t k = __popcll(m);
+    start -= k + 2;
+    const bool mine = ((m >> lane) & 1ull) != 0;
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
+    const uint32_t *row = row_end - 2 - k;
+    return live && mine ? row[below] : kListIdle;
+}
+
 template <bool COUNT>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVES))) void k_adjoint_list(
     const float4 *__restrict__ records, const int32_t *__restrict__ inv, const Ptrs ptr, const RenderParams P)
@@ -1194,7 +1220,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
     const int xcd = xcd_id();
     int qi = 0;
     uint64_t c_pkt = 0, c_lcomp = 0, c_group = 0;
-    const ListPool pool = ptr.pool;
+    // the pool is only read here
+    const uint32_t *__restrict__ slots = ptr.pool.slots;
+    const int32_t *__restrict__ prev = ptr.pool.prev;
+    const int32_t *__restrict__ fill = ptr.pool.fill;
     for (;;) {
         const int64_t pkt = next_packet(P, ptr.queue, lane, xcd, qi, iter_pkt);
         if (pkt >= P.n_packets) break;
@@ -1217,27 +1246,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
         // the packet's last chunk (lane 0 always holds one of the packet's rays)
         int32_t chunk = __builtin_amdgcn_readfirstlane(li.z);
         if (!wave_ballot(live) || chunk < 0) continue;
-        // rows are walked from the last to the first: a row ends with its lane mask, so the
-        // mask at the row's end gives its start, which is the previous row's end
-        int32_t end = pool.fill[chunk];
-        for (;;) {
-            while (end == 0 && chunk >= 0) {
-                chunk = pool.prev[chunk];
-                end = chunk >= 0 ? pool.fill[chunk] : 0;
-            }
-            if (chunk < 0) break;
-            const uint32_t *row_end = pool.slots + int64_t(chunk) * kChunkSlots + end;
-            const uint64_t m = uint64_t(row_end[-2]) | (uint64_t(row_end[-1]) << 32);
-            const int32_t k = __popcll(m);
-            end -= k + 2;
-            const uint32_t *row = row_end - 2 - k;
-            const bool mine = ((m >> lane) & 1ull) != 0;
-            const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-            const uint32_t e = live && mine ? row[below] : kListIdle;
-            const bool act = e != kListIdle;
+        // Rows are walked from the last to the first: a row ends with its lane mask, so the
+        // mask at the row's end gives its start, which is the previous row's end. The next
+        // row's mask and this lane's entry in it are loaded while a row is processed.
+        int32_t start = fill[chunk];
+        row_seek(prev, fill, chunk, start);
+        uint32_t e = kListIdle;
+        if (chunk >= 0) e = row_entry(slots, chunk, start, live, lane);
+        while (chunk >= 0) {
+            int32_t nchunk = chunk, nstart = start;
+            row_seek(prev, fill, nchunk, nstart);
+            uint32_t ne = kListIdle;
+            if (nchunk >= 0) ne = row_entry(slots, nchunk, nstart, live, lane);
+            chunk = nchunk;
+            start = nstart;
+            const uint32_t cur = e;
+            e = ne;
+            const bool act = cur != kListIdle;
             if (!wave_ballot(act)) continue;
-            const bool comp = act && e < kListSecond;
-            const uint32_t gid = e & ~kListSecond;
+            const bool comp = act && cur < kListSecond;
+            const uint32_t gid = cur & ~kListSecond;
             HitData H;
             recompute_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P.Q, H);
             const float Tk = back_T(B, H.al);
