@@ -76,8 +76,10 @@ struct HitGeom {
     float y0, y1, y2, e0, e1, e2, u0, u1, u2, b, ia;
 };
 
-__device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
-                                     float Q, float &t1, float &h2, HitGeom &G)
+// The test in two parts, so a wave can skip the second when no lane's ray meets the ellipsoid.
+// First part: the whitened geometry and h^2.
+__device__ inline float ellipsoid_h2(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                     HitGeom &G)
 {
     const float xx = ray.ox - r3.x, xy = ray.oy - r3.y, xz = ray.oz - r3.z;
     // rows of R^T
@@ -101,16 +103,31 @@ __device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const floa
     const float b = o0 * d0 + o1 * d1 + o2 * d2;
     const float uu = u0 * u0 + u1 * u1 + u2 * u2;
     const float ia = __builtin_amdgcn_rcpf(a);
-    h2 = uu * ia;
     G = HitGeom{y0, y1, y2, e0, e1, e2, u0, u1, u2, b, ia};
-    // both root forms for every lane and a select, no divergent branch (t1 is only used
-    // where the ray hits, h2 <= Q, and there the chosen form is the same arithmetic)
-    const float sq = __builtin_amdgcn_sqrtf((Q - h2) * ia);  // hardware square root (1 ulp)
-    const float tc = -b * ia;
+    return uu * ia;
+}
+
+// Second part: the nearer root t1 (meaningful where h2 <= Q). Both root forms are computed for
+// every lane and one is selected, no divergent branch (where the ray hits the chosen form is
+// the same arithmetic).
+__device__ inline float ellipsoid_t1(const HitGeom &G, const float4 r2, float h2, float Q)
+{
+    const float D0 = r2.y, D1 = r2.z, D2 = r2.w;
+    const float o0 = D0 * G.y0, o1 = D1 * G.y1, o2 = D2 * G.y2;
+    const float sq = __builtin_amdgcn_sqrtf((Q - h2) * G.ia);  // hardware square root (1 ulp)
+    const float tc = -G.b * G.ia;
     const float oo = o0 * o0 + o1 * o1 + o2 * o2;
-    const float t_viete = ((oo - Q) * ia) * __builtin_amdgcn_rcpf(tc + sq);
-    t1 = b >= 0.0f ? tc - sq : t_viete;
+    const float t_viete = ((oo - Q) * G.ia) * __builtin_amdgcn_rcpf(tc + sq);
+    float t1 = G.b >= 0.0f ? tc - sq : t_viete;
     if (t1 == 0.0f) t1 = 0.0f;  // -0 -> +0 so the key order matches float order
+    return t1;
+}
+
+__device__ inline bool ellipsoid_hit(const Ray &ray, const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                     float Q, float &t1, float &h2, HitGeom &G)
+{
+    h2 = ellipsoid_h2(ray, r0, r1, r2, r3, G);
+    t1 = ellipsoid_t1(G, r2, h2, Q);
     return h2 <= Q;
 }
 
@@ -906,18 +923,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                              r3 = records[4 * js + 3];
                 const uint32_t gid = uint32_t(gidx[js]);
                 // every lane evaluates the test and the key (no divergent branch); only lanes
-                // whose ray hits take part
-                float t1 = 0.0f, h2 = 0.0f;
+                // whose ray hits take part, and the entry distance and key only when one does
                 HitGeom hg;
-                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2, hg);
-                const double k = hit_key(t1, gid);
-                const bool cand = live && hit && t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
-                const uint64_t cmask = wave_ballot(cand);
+                const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
                 if (COUNT) {
                     ++c_leaf;
                     c_lleaf += __popcll(wave_ballot(live));
-                    c_lbuf += __popcll(cmask);
                 }
+                if (!wave_ballot(live && h2 <= P.Q)) return;
+                const float t1 = ellipsoid_t1(hg, r2, h2, P.Q);
+                const double k = hit_key(t1, gid);
+                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
+                const uint64_t cmask = wave_ballot(cand);
+                if (COUNT) c_lbuf += __popcll(cmask);
                 if (cmask) {
                     // every lane runs the insertion network; lanes without a candidate insert
                     // the empty key, which moves nothing
@@ -1100,17 +1118,18 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
                              r3 = records[4 * js + 3];
                 const uint32_t gid = uint32_t(gidx[js]);
-                float t1 = 0.0f, h2 = 0.0f;
                 HitGeom hg;
-                const bool hit = ellipsoid_hit(ray, r0, r1, r2, r3, P.Q, t1, h2, hg);
-                const double k = hit_key(t1, gid);
-                const bool cand = live && hit && t1 >= P.t_min && t1 < tmax && k < hi && -k < hb.key[K - 1];
-                const uint64_t cmask = wave_ballot(cand);
+                const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
                 if (COUNT) {
                     ++c_leaf;
                     c_lleaf += __popcll(wave_ballot(live));
-                    c_lbuf += __popcll(cmask);
                 }
+                if (!wave_ballot(live && h2 <= P.Q)) return;
+                const float t1 = ellipsoid_t1(hg, r2, h2, P.Q);
+                const double k = hit_key(t1, gid);
+                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k < hi && -k < hb.key[K - 1];
+                const uint64_t cmask = wave_ballot(cand);
+                if (COUNT) c_lbuf += __popcll(cmask);
                 if (cmask) {
                     hb.insert(cand ? -k : kNoHit);
                     if (hb.key[K - 1] != kNoHit) t_lo = fmaxf(P.t_min, hit_key_t(-hb.key[K - 1]));
