@@ -76,6 +76,9 @@ def parse():
     ap.add_argument("--loss", choices=("l1", "paper"), default="l1",
                     help="l1: mean L1 (gradient by torch); paper: (1 - 0.2) L2 + 0.2 D-SSIM per view (rs_loss)")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="JSON file of autotuned launch shapes keyed by GPU architecture, library build and "
+                         "workload: a hit skips the tuning, a miss tunes and stores")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-recompute", action="store_true", help="skip the re-traversing adjoint's step")
     ap.add_argument("--no-batching", action="store_true", help="skip the batched vs per-view comparison")
@@ -258,7 +261,22 @@ def main():
     pf = pb = base
     tune = None
     if not fixed and not args.no_autotune and not args.profile:
-        pf, pb, tune = tune_for(base)
+        cache = key = hit = None
+        if args.tune_cache:
+            from paper_2501_19196_amd import _lib as RL, tune_cache as TC
+            cache = TC.TuneCache(args.tune_cache)
+            extra = dict(workload=w["name"], mesh_triangles=mesh_np.n_tris if mesh_np is not None else 0,
+                         bounces=shading.max_bounces if shading is not None else 0)
+            key = TC.make_key(torch.cuda.get_device_properties(0).gcnArchName, TC.library_digest(RL.LIB_PATH), n, nr,
+                              views, base, extra)
+            hit = cache.get(key)
+        if hit is not None:
+            pf, pb = TC.apply_shape(base, hit[0]), TC.apply_shape(base, hit[1])
+            tune = dict(fwd=hit[0], bwd=hit[1], cached=True)
+        else:
+            pf, pb, tune = tune_for(base)
+            if cache is not None:
+                cache.put(key, pf, pb, note=w["name"])
         log("autotune", tune)
 
     lws = [R.loss_workspace(vw, vh, dev) for _, vw, vh in views] if args.loss == "paper" else None
