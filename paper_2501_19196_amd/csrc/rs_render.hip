@@ -160,6 +160,8 @@ struct HitBuf {
 #pragma unroll
         for (int s = 0; s < K; ++s) key[s] = kNoHit;
     }
+    __device__ inline double front() const { return key[0]; }
+    __device__ inline double last() const { return key[K - 1]; }
 
     // drop the front entry (static register moves: no dynamic indexing)
     __device__ inline void pop_front()
@@ -184,6 +186,85 @@ struct HitBuf {
             k = hi;
         }
     }
+};
+
+// The same sorted buffer of KR + KT keys with its last KT entries in LDS: a per-wave ring of KT
+// slots of 64 lanes (slot-major, so one slot of the wave is one contiguous 512-byte row) whose
+// wave-uniform head is the tail's first entry. The registers hold the KR smallest keys. An
+// insertion runs the register chain, then carries its key on through the tail when some lane
+// carries one; a pop shifts the registers and takes the tail's first entry into the last one.
+// `kmax` mirrors the buffer's last entry, so the candidate test and the culling bound need no
+// LDS read. The workgroup is one wave.
+template <int KR, int KT>
+struct HitBufTail {
+    double key[KR];
+    double kmax;
+    int32_t head;
+    double *ring;  // this wave's LDS ring, KT x 64 doubles
+    int lane;
+
+    __device__ inline void clear()
+    {
+#pragma unroll
+        for (int s = 0; s < KR; ++s) key[s] = kNoHit;
+        kmax = kNoHit;
+        head = 0;
+#pragma unroll
+        for (int i = 0; i < KT; ++i) ring[i * kWave + lane] = kNoHit;
+    }
+    __device__ inline double front() const { return key[0]; }
+    __device__ inline double last() const { return kmax; }
+
+    __device__ inline void pop_front()
+    {
+#pragma unroll
+        for (int s = 0; s + 1 < KR; ++s) key[s] = key[s + 1];
+        double *e = ring + head * kWave + lane;
+        key[KR - 1] = *e;
+        *e = kNoHit;
+        head = head + 1 == KT ? 0 : head + 1;
+        kmax = kNoHit;
+    }
+
+    __device__ inline void insert(double k)
+    {
+#pragma unroll
+        for (int s = 0; s < KR; ++s) {
+            double hi = 0.0;
+            asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
+            asm volatile("v_min_f64 %0, %0, %1" : "+v"(key[s]) : "v"(k));
+            k = hi;
+        }
+        if (!wave_ballot(k != kNoHit)) return;  // every carried key fell into an empty register slot
+        int32_t p = head;
+#pragma unroll
+        for (int i = 0; i < KT; ++i) {
+            double *e = ring + p * kWave + lane;
+            double t = *e;
+            double hi = 0.0;
+            if (i + 1 < KT) asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(t), "v"(k));
+            asm volatile("v_min_f64 %0, %0, %1" : "+v"(t) : "v"(k));
+            *e = t;
+            if (i + 1 == KT) kmax = t;
+            k = hi;
+            p = p + 1 == KT ? 0 : p + 1;
+        }
+    }
+};
+
+// The forward's buffer for a hit-buffer size K. At K = 48 the last 16 keys live in LDS (8 KB
+// per wave): 32 keys in registers let the kernel run four waves per SIMD instead of three,
+// which hides more of the node and record fetch latency than the LDS traffic of the tail costs
+// (measured: 9.6 against 10.5 ms at the scene-scale workload; 28 + 20 keys 9.7, 36 + 12 9.6,
+// 40 + 8 10.3).
+constexpr int kTailKeys = 16;
+template <int K>
+struct FwdBuf {
+    using type = HitBuf<K>;
+};
+template <>
+struct FwdBuf<48> {
+    using type = HitBufTail<48 - kTailKeys, kTailKeys>;
 };
 
 // ------------------------------------------------------------- compositing
@@ -824,8 +905,9 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
 // (512 / waves): the adjoint carries the gradient temporaries as well. The
 // forward targets are measured optima: a few dozen bytes of scratch spills
-// (kbuf 24 at five waves, 48 at three) cost less than the node-fetch latency
-// the extra wave hides, while larger spills (kbuf 24 at six, 32 at five) lose.
+// (kbuf 24 at five waves, 48 at four with its LDS tail) cost less than the
+// node-fetch latency the extra wave hides, while larger spills (kbuf 24 at six,
+// 32 at five) lose.
 // The adjoint's are measured the same way: kbuf 24 and 32 at four waves and
 // 48 at three beat one wave fewer by 10-20 %, while one wave more (five, and
 // four for 48) spills heavily and doubles the time.
@@ -851,7 +933,7 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
 #define RS_FWD32_WAVES 4
 #endif
 #ifndef RS_FWD48_WAVES
-#define RS_FWD48_WAVES 3
+#define RS_FWD48_WAVES 4
 #endif
 constexpr int waves_for(int K, bool bwd)
 {
@@ -909,7 +991,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
         bool overflow = false;
 
         while (wave_ballot(live)) {
-            HitBuf<K> hb;
+            typename FwdBuf<K>::type hb;
+            if constexpr (!std::is_same<typename FwdBuf<K>::type, HitBuf<K>>::value) {
+                __shared__ double ring[kTailKeys * kWave];
+                hb.ring = ring;
+                hb.lane = lane;
+            }
             hb.clear();
             if (COUNT) ++c_round;
             // NaN on lanes that are not live: no box test passes for them
@@ -933,14 +1020,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 if (!wave_ballot(live && h2 <= P.Q)) return;
                 const float t1 = ellipsoid_t1(hg, r2, h2, P.Q);
                 const double k = hit_key(t1, gid);
-                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k > last && k < hb.key[K - 1];
+                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k > last && k < hb.last();
                 const uint64_t cmask = wave_ballot(cand);
                 if (COUNT) c_lbuf += __popcll(cmask);
                 if (cmask) {
                     // every lane runs the insertion network; lanes without a candidate insert
                     // the empty key, which moves nothing
                     hb.insert(cand ? k : kNoHit);
-                    if (hb.key[K - 1] != kNoHit) t_hi_w = widen(fminf(tmax, hit_key_t(hb.key[K - 1])), sl.pad);
+                    if (hb.last() != kNoHit) t_hi_w = widen(fminf(tmax, hit_key_t(hb.last())), sl.pad);
                 }
             };
 
@@ -960,10 +1047,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 
             // composite this round's hits front to back; alpha is recomputed from the record
             // with the leaf test's own arithmetic. The buffer is consumed from its front.
-            const double round_last = hb.key[K - 1];
+            const double round_last = hb.last();
             bool more = true;
             for (int s = 0; s < K; ++s) {
-                const double key_s = hb.key[0];
+                const double key_s = hb.front();
                 hb.pop_front();
                 const bool act = more && live && key_s != kNoHit;
                 const uint64_t act_mask = wave_ballot(act);
