@@ -256,7 +256,7 @@ struct HitBufTail {
 // per wave): 32 keys in registers let the kernel run four waves per SIMD instead of three,
 // which hides more of the node and record fetch latency than the LDS traffic of the tail costs
 // (measured: 9.6 against 10.5 ms at the scene-scale workload; 28 + 20 keys 9.7, 36 + 12 9.6,
-// 40 + 8 10.3).
+// 40 + 8 10.3). At K = 32 the same split loses (16 + 16 keys at five waves: 10.5 against 10.3).
 constexpr int kTailKeys = 16;
 template <int K>
 struct FwdBuf {
