@@ -290,9 +290,9 @@ def _full_size_sampled(k, n_samples, seed, hit_list, label):
 
 
 @pytest.mark.timeout(600)
-@pytest.mark.parametrize("hit_list", [512, 0])
+@pytest.mark.parametrize("hit_list", [64, 512, 0])
 def test_scene_scale_sampled_gradients(hit_list):
-    """1M Gaussians, 1920x1080, 8,000 sampled pixels."""
+    """1M Gaussians, 1920x1080, 8,000 sampled pixels (64 slots per ray: the benchmark's pool)."""
     print("case scene-scale sampled grads", hit_list, flush=True)
     _full_size_sampled(4, 8000, 41, hit_list, f"scene-scale 8000 px lists {hit_list}")
 
