@@ -153,6 +153,7 @@ __device__ inline uint32_t hit_key_gid(double k) { return uint32_t(uint64_t(__do
 
 template <int K>
 struct HitBuf {
+    static constexpr int size = K;
     double key[K];  // sorted ascending; kNoHit marks an empty slot
 
     __device__ inline void clear()
@@ -197,6 +198,7 @@ struct HitBuf {
 // LDS read. The workgroup is one wave.
 template <int KR, int KT>
 struct HitBufTail {
+    static constexpr int size = KR + KT;
     double key[KR];
     double kmax;
     int32_t head;
@@ -1049,7 +1051,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             // with the leaf test's own arithmetic. The buffer is consumed from its front.
             const double round_last = hb.last();
             bool more = true;
-            for (int s = 0; s < K; ++s) {
+            for (int s = 0; s < hb.size; ++s) {
                 const double key_s = hb.front();
                 hb.pop_front();
                 const bool act = more && live && key_s != kNoHit;
