@@ -725,6 +725,9 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
 #pragma unroll
             for (int v = 0; v < 13; ++v) r[v] = G.v[v];
         }
+        // the segments read other lanes' rows and descriptors: a (one-wave) barrier keeps the
+        // compiler from reusing a lane's own earlier stores in their place
+        __syncthreads();
         const int v = lane & 15;
         for (int b = 0; b < ng; b += 4) {
             const int gi = b + (lane >> 4);
