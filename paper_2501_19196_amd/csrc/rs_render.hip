@@ -467,15 +467,22 @@ __device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__
     return r3.w * __expf(-0.5f * h2);
 }
 
-// alpha, colour and test intermediates of a hit (no compositing)
+// alpha, colour and test intermediates of a hit (no compositing). EVERY: every lane
+// computes, the caller giving idle lanes a valid Gaussian index whose values it never
+// uses, so no lane is masked off and nothing is zeroed first.
+template <bool EVERY = false>
 __device__ inline void recompute_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
                                      const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc, float Q,
                                      HitData &H)
 {
-    H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = H.Tk = 0.0f;
-    H.g = HitGeom{};
-    if (act) {
+    H.Tk = 0.0f;
+    if (!EVERY) {
+        H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = 0.0f;
+        H.g = HitGeom{};
+    }
+    if (EVERY || act) {
         H.al = hit_alpha(gid, ray, records, inv, Q, H.r0, H.r1, H.r2, H.r3, H.t1, H.h2, H.g);
+        H.cr = H.cg = H.cb = 0.0f;
         if (!zc) {
             H.cr = rgb[3 * gid];
             H.cg = rgb[3 * gid + 1];
@@ -642,9 +649,13 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
                                    const Back &B, const LaneGrad &Gd, bool zc, float *gacc, int lane, uint64_t &c_group)
 {
     GradOut G;
+    // the table path sums neighbouring lanes' values, so idle lanes contribute zeros; the
+    // stored-list path stores active lanes' values only and computes on every lane
+    if (TABLE) {
 #pragma unroll
-    for (int v = 0; v < 13; ++v) G.v[v] = 0.0f;
-    if (act) {
+        for (int v = 0; v < 13; ++v) G.v[v] = 0.0f;
+    }
+    if (!TABLE || act) {
         const float dLda = Tk * (Gd.gr * (H.cr - B.Sr) + Gd.gg * (H.cg - B.Sg) + Gd.gb * (H.cb - B.Sb));
         grad_hit(H.r2, H.g, H.h2, dLda, H.al, G);
         const float wgt = H.al * Tk;
@@ -1376,9 +1387,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(RS_LIST_WAVE
             const bool act = cur != kListIdle;
             if (!wave_ballot(act)) continue;
             const bool comp = act && cur < kListSecond;
-            const uint32_t gid = cur & ~kListSecond;
+            const uint32_t gid = act ? cur & ~kListSecond : 0u;  // idle lanes read Gaussian 0 (unused)
             HitData H;
-            recompute_hit(act, gid, LR.ray, records, inv, ptr.rgb, zc, P.Q, H);
+            recompute_hit<true>(act, gid, LR.ray, records, inv, ptr.rgb, zc, P.Q, H);
             const float Tk = back_T(B, H.al);
             const uint64_t comp_mask = wave_ballot(comp);
             if (COUNT) c_lcomp += __popcll(comp_mask);
