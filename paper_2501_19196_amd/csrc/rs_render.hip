@@ -702,34 +702,34 @@ __device__ inline void adjoint_hit(bool act, uint64_t act_mask, uint32_t gid, co
     } else {
         // Lanes holding the same Gaussian form a group; groups are numbered in order of their
         // lowest lane and each group's lanes store their 13 values in consecutive LDS rows. The
-        // scalar loop keeps only masks and counts in scalar registers; a lane records its row
-        // and group, and after the loop each group's lowest lane writes the group's (Gaussian,
-        // first row), the next group's first row closing it. Then 16-lane segments sum one
+        // scalar loop keeps only masks and counts in scalar registers; a lane records its row,
+        // and after the loop each group's lowest lane writes the group's (Gaussian, first row),
+        // the next group's first row closing it. Then 16-lane segments sum one
         // group's rows each, so one atomic instruction adds the totals of four Gaussians (one
         // 64-byte accumulator line per segment). The wave is the whole workgroup, and its LDS
         // operations complete in order.
         __shared__ float rows[kWave * 16];
         __shared__ int2 groups[kWave + 1];  // Gaussian index, first row
         uint64_t todo = act_mask, leaders = 0;
-        bool pend = act;  // not yet in a group (a lane mask, like todo)
-        int32_t ng = 0, pos = 0, mypos = 0, mygrp = 0;
+        int32_t pos = 0, mypos = 0;
         while (todo) {
             const int leader = __builtin_ctzll(todo);
             const uint32_t lg = __builtin_amdgcn_readlane(gid, leader);
-            const bool mine = pend && gid == lg;
-            const uint64_t same = wave_ballot(gid == lg) & todo;  // the lanes of mine, as a mask
+            const uint64_t same = wave_ballot(gid == lg) & todo;
+            const bool mine = __builtin_amdgcn_inverse_ballot_w64(same);  // this lane is in the group
             todo &= ~same;
-            pend = pend && !mine;
             leaders |= 1ull << leader;
             if (COUNT) ++c_group;
             const int32_t at = int32_t(
                 __builtin_amdgcn_mbcnt_hi(uint32_t(same >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(same), uint32_t(pos))));
             mypos = mine ? at : mypos;
-            mygrp = mine ? ng : mygrp;
-            ++ng;
             pos += __popcll(same);
         }
-        if ((leaders >> lane) & 1ull) groups[mygrp] = make_int2(int32_t(gid), mypos);
+        const int32_t ng = __popcll(leaders);
+        // a group's number is the number of leaders below its leader (groups open in lane order)
+        const int32_t mygrp = int32_t(
+            __builtin_amdgcn_mbcnt_hi(uint32_t(leaders >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(leaders), 0u)));
+        if (__builtin_amdgcn_inverse_ballot_w64(leaders)) groups[mygrp] = make_int2(int32_t(gid), mypos);
         if (lane == 0) groups[ng] = make_int2(0, pos);
         if (act) {
             float *r = rows + 16 * mypos;
