@@ -1020,6 +1020,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 !live ? __builtin_nanf("") : (last == -kNoHit ? P.t_min : fmaxf(P.t_min, hit_key_t(last)));
             float t_hi_w = widen(tmax, sl.pad);
 
+            // the round's live lanes as a mask: the leaf step combines per-compare masks with it
+            // (a ballot of a compound condition would first turn it into a vector value)
+            const uint64_t live_now = wave_ballot(live);
             auto leaf = [&](int64_t j) {
                 const int64_t js = __builtin_amdgcn_readfirstlane(int32_t(j));
                 const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
@@ -1031,13 +1034,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
                 if (COUNT) {
                     ++c_leaf;
-                    c_lleaf += __popcll(wave_ballot(live));
+                    c_lleaf += __popcll(live_now);
                 }
-                if (!wave_ballot(live && h2 <= P.Q)) return;
+                const uint64_t hmask = wave_ballot(h2 <= P.Q) & live_now;
+                if (!hmask) return;
                 const float t1 = ellipsoid_t1(hg, r2, h2, P.Q);
                 const double k = hit_key(t1, gid);
-                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k > last && k < hb.last();
-                const uint64_t cmask = wave_ballot(cand);
+                const uint64_t cmask = hmask & wave_ballot(t1 >= P.t_min) & wave_ballot(t1 < tmax) &
+                                       wave_ballot(k > last) & wave_ballot(k < hb.last());
+                const bool cand = __builtin_amdgcn_inverse_ballot_w64(cmask);
                 if (COUNT) c_lbuf += __popcll(cmask);
                 if (cmask) {
                     // every lane runs the insertion network; lanes without a candidate insert
@@ -1216,6 +1221,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             float t_lo = !live ? __builtin_nanf("") : P.t_min;  // rises to the K-th largest t
             const float t_hi_w = widen(hit_key_t(hi), sl.pad);
 
+            const uint64_t live_now = wave_ballot(live);  // as in the forward's leaf step
             auto leaf = [&](int64_t j) {
                 const int64_t js = __builtin_amdgcn_readfirstlane(int32_t(j));
                 const float4 r0 = records[4 * js + 0], r1 = records[4 * js + 1], r2 = records[4 * js + 2],
@@ -1225,13 +1231,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
                 if (COUNT) {
                     ++c_leaf;
-                    c_lleaf += __popcll(wave_ballot(live));
+                    c_lleaf += __popcll(live_now);
                 }
-                if (!wave_ballot(live && h2 <= P.Q)) return;
+                const uint64_t hmask = wave_ballot(h2 <= P.Q) & live_now;
+                if (!hmask) return;
                 const float t1 = ellipsoid_t1(hg, r2, h2, P.Q);
                 const double k = hit_key(t1, gid);
-                const bool cand = live && h2 <= P.Q && t1 >= P.t_min && t1 < tmax && k < hi && -k < hb.key[K - 1];
-                const uint64_t cmask = wave_ballot(cand);
+                const uint64_t cmask = hmask & wave_ballot(t1 >= P.t_min) & wave_ballot(t1 < tmax) & wave_ballot(k < hi) &
+                                       wave_ballot(-k < hb.key[K - 1]);
+                const bool cand = __builtin_amdgcn_inverse_ballot_w64(cmask);
                 if (COUNT) c_lbuf += __popcll(cmask);
                 if (cmask) {
                     hb.insert(cand ? -k : kNoHit);
