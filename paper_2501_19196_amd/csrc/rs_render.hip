@@ -859,25 +859,30 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
             ++c_node;
             c_lchild += __popcll(bl) + __popcll(br);
         }
-        if (bl != 0 && br != 0) {
+        // nonzero iff both children are entered (one scalar compare for the branch)
+        const uint32_t both = min(uint32_t(__popcll(bl)), uint32_t(__popcll(br)));
+        int32_t next;
+        if (both != 0) {
             // both entered: the child the leader lane (lowest live lane) reaches first (REV: leaves
             // last) goes first
             const bool lfirst = (wave_ballot(REV ? lf >= rf : ln <= rn) & lead_bit) != 0;
             if (sp >= stack_depth) {
                 overflow = true;
-                return kDone;
+                next = kDone;
+            } else {
+                stackv = (lane == sp) ? (lfirst ? right : left) : stackv;
+                ++sp;
+                next = lfirst ? left : right;
             }
-            stackv = (lane == sp) ? (lfirst ? right : left) : stackv;
-            ++sp;
-            node = lfirst ? left : right;
         } else if ((bl | br) != 0) {
-            node = bl != 0 ? left : right;
+            next = bl != 0 ? left : right;
         } else if (sp == 0) {
-            return kDone;
+            next = kDone;
         } else {
             --sp;
-            node = __builtin_amdgcn_readlane(stackv, sp);
+            next = __builtin_amdgcn_readlane(stackv, sp);
         }
+        node = next;
     }
     return node;
 }
