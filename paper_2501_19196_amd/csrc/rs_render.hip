@@ -887,15 +887,10 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
     return node;
 }
 
-#define RS_DESCEND_CASE(O)                                                                                    \
-    case O:                                                                                                   \
-        node = descend<O, COUNT, kRev>(node, nodes, sl, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,       \
-                                       stackv, overflow, c_node, c_lchild);                                   \
-        break;
-
 // The wave-uniform walk of the whole BVH for one round: descend to a leaf, test it
-// (leaf(j), which may move t_lo / t_hi_w), resume from the stack.
-#define RS_WALK_BVH()                                                                                         \
+// (leaf(j), which may move t_lo / t_hi_w), resume from the stack. The walk is specialised on the
+// wave's direction octant as a whole, so the octant is dispatched once per walk.
+#define RS_WALK_OCT(O)                                                                                        \
     {                                                                                                         \
         int32_t node = P.root;                                                                                \
         int32_t sp = 0;                                                                                       \
@@ -903,24 +898,27 @@ __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes
         const uint64_t live_mask = wave_ballot(live);                                                         \
         const uint64_t lead_bit = live_mask & (~live_mask + 1);                                               \
         for (;;) {                                                                                            \
-            switch (oct) {                                                                                    \
-                RS_DESCEND_CASE(0)                                                                            \
-                RS_DESCEND_CASE(1)                                                                            \
-                RS_DESCEND_CASE(2)                                                                            \
-                RS_DESCEND_CASE(3)                                                                            \
-                RS_DESCEND_CASE(4)                                                                            \
-                RS_DESCEND_CASE(5)                                                                            \
-                RS_DESCEND_CASE(6)                                                                            \
-                RS_DESCEND_CASE(7)                                                                            \
-            default:                                                                                          \
-                RS_DESCEND_CASE(kMixedOctant)                                                                 \
-            }                                                                                                 \
+            node = descend<O, COUNT, kRev>(node, nodes, sl, lead_bit, t_lo, t_hi_w, lane, P.stack_depth, sp,  \
+                                           stackv, overflow, c_node, c_lchild);                               \
             if (node == kDone) break;                                                                         \
             leaf(~node);                                                                                      \
             if (sp == 0) break;                                                                               \
             --sp;                                                                                             \
             node = __builtin_amdgcn_readlane(stackv, sp);                                                     \
         }                                                                                                     \
+    }
+
+#define RS_WALK_BVH()                                                                                         \
+    switch (oct) {                                                                                            \
+    case 0: RS_WALK_OCT(0) break;                                                                             \
+    case 1: RS_WALK_OCT(1) break;                                                                             \
+    case 2: RS_WALK_OCT(2) break;                                                                             \
+    case 3: RS_WALK_OCT(3) break;                                                                             \
+    case 4: RS_WALK_OCT(4) break;                                                                             \
+    case 5: RS_WALK_OCT(5) break;                                                                             \
+    case 6: RS_WALK_OCT(6) break;                                                                             \
+    case 7: RS_WALK_OCT(7) break;                                                                             \
+    default: RS_WALK_OCT(kMixedOctant) break;                                                                 \
     }
 
 // Occupancy target (waves per SIMD) of each variant, i.e. its VGPR budget
