@@ -1035,6 +1035,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 // whose ray hits take part, and the entry distance and key only when one does
                 HitGeom hg;
                 const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
+                // the index load is issued with the record's (its latency hides behind theirs)
+                asm volatile("" ::"s"(gid));
                 if (COUNT) {
                     ++c_leaf;
                     c_lleaf += __popcll(live_now);
@@ -1232,6 +1234,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                 const uint32_t gid = uint32_t(gidx[js]);
                 HitGeom hg;
                 const float h2 = ellipsoid_h2(ray, r0, r1, r2, r3, hg);
+                // the index load is issued with the record's (its latency hides behind theirs)
+                asm volatile("" ::"s"(gid));
                 if (COUNT) {
                     ++c_leaf;
                     c_lleaf += __popcll(live_now);
