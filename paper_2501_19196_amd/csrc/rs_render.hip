@@ -453,18 +453,25 @@ struct HitData {
     HitGeom g;
 };
 
-// alpha of Gaussian gid along the ray, with the leaf test's own arithmetic
-__device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
-                                  const int32_t *__restrict__ inv, float Q, float4 &r0, float4 &r1, float4 &r2,
-                                  float4 &r3, float &t1, float &h2, HitGeom &G)
+// alpha of the Gaussian at sorted position js along the ray, with the leaf test's own arithmetic
+__device__ inline float hit_alpha_at(int32_t js, const Ray &ray, const float4 *__restrict__ records, float Q,
+                                     float4 &r0, float4 &r1, float4 &r2, float4 &r3, float &t1, float &h2,
+                                     HitGeom &G)
 {
-    const int32_t js = inv[gid];
     r0 = records[4 * js + 0];
     r1 = records[4 * js + 1];
     r2 = records[4 * js + 2];
     r3 = records[4 * js + 3];
     ellipsoid_hit(ray, r0, r1, r2, r3, Q, t1, h2, G);
     return r3.w * __expf(-0.5f * h2);
+}
+
+// the same for Gaussian gid
+__device__ inline float hit_alpha(uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
+                                  const int32_t *__restrict__ inv, float Q, float4 &r0, float4 &r1, float4 &r2,
+                                  float4 &r3, float &t1, float &h2, HitGeom &G)
+{
+    return hit_alpha_at(inv[gid], ray, records, Q, r0, r1, r2, r3, t1, h2, G);
 }
 
 // alpha, colour and test intermediates of a hit (no compositing). EVERY: every lane
@@ -491,11 +498,21 @@ __device__ inline void recompute_hit(bool act, uint32_t gid, const Ray &ray, con
     }
 }
 
-__device__ inline void composite_hit(bool act, uint32_t gid, const Ray &ray, const float4 *__restrict__ records,
-                                     const int32_t *__restrict__ inv, const float *__restrict__ rgb, bool zc,
+// (js: the hit's sorted position, looked up by the caller ahead of time)
+__device__ inline void composite_hit(bool act, uint32_t gid, int32_t js, const Ray &ray,
+                                     const float4 *__restrict__ records, const float *__restrict__ rgb, bool zc,
                                      const RenderParams &P, Accum &A, HitData &H)
 {
-    recompute_hit(act, gid, ray, records, inv, rgb, zc, P.Q, H);
+    H.al = H.cr = H.cg = H.cb = H.t1 = H.h2 = 0.0f;
+    H.g = HitGeom{};
+    if (act) {
+        H.al = hit_alpha_at(js, ray, records, P.Q, H.r0, H.r1, H.r2, H.r3, H.t1, H.h2, H.g);
+        if (!zc) {
+            H.cr = rgb[3 * gid];
+            H.cg = rgb[3 * gid + 1];
+            H.cb = rgb[3 * gid + 2];
+        }
+    }
     H.Tk = A.T;
     if (act) composite_step(A, H.al, H.cr, H.cg, H.cb);
 }
@@ -1075,9 +1092,14 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             // with the leaf test's own arithmetic. The buffer is consumed from its front.
             const double round_last = hb.last();
             bool more = true;
+            // the sorted position of the buffer's front key is looked up one step ahead, so its
+            // latency overlaps the previous step (an empty key reads position 0, unused)
+            int32_t js_next = inv[hb.front() != kNoHit ? hit_key_gid(hb.front()) : 0u];
             for (int s = 0; s < hb.size; ++s) {
                 const double key_s = hb.front();
+                const int32_t js_s = js_next;
                 hb.pop_front();
+                js_next = inv[hb.front() != kNoHit ? hit_key_gid(hb.front()) : 0u];
                 const bool act = more && live && key_s != kNoHit;
                 const uint64_t act_mask = wave_ballot(act);
                 more = act_mask != 0;
@@ -1093,7 +1115,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                             float4 r0, r1, r2, r3;
                             float t1, h2;
                             HitGeom hg;
-                            const float al = hit_alpha(gid, ray, records, inv, P.Q, r0, r1, r2, r3, t1, h2, hg);
+                            const float al = hit_alpha_at(js_s, ray, records, P.Q, r0, r1, r2, r3, t1, h2, hg);
                             entry = gid | kListSecond;
                             T2 *= 1.0f - al;
                             ++extra;
@@ -1102,7 +1124,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
                     }
                 } else {
                     HitData H;
-                    composite_hit(act, gid, ray, records, inv, ptr.rgb, zc, P, A, H);
+                    composite_hit(act, gid, js_s, ray, records, ptr.rgb, zc, P, A, H);
                     if (act) {
                         entry = gid;
                         last = key_s;
