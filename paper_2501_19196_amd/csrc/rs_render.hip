@@ -196,6 +196,9 @@ struct HitBuf {
 // carries one; a pop shifts the registers and takes the tail's first entry into the last one.
 // `kmax` mirrors the buffer's last entry, so the candidate test and the culling bound need no
 // LDS read. The workgroup is one wave.
+#ifndef RS_RING_GROUP
+#define RS_RING_GROUP 8
+#endif
 template <int KR, int KT>
 struct HitBufTail {
     static constexpr int size = KR + KT;
@@ -238,18 +241,32 @@ struct HitBufTail {
             k = hi;
         }
         if (!wave_ballot(k != kNoHit)) return;  // every carried key fell into an empty register slot
+        // the ring's entries are read RG at a time (their LDS reads in flight together), then
+        // passed through the min/max chain and written back
+        constexpr int RG = RS_RING_GROUP;
+        static_assert(KT % RG == 0, "ring group");
         int32_t p = head;
 #pragma unroll
-        for (int i = 0; i < KT; ++i) {
-            double *e = ring + p * kWave + lane;
-            double t = *e;
-            double hi = 0.0;
-            if (i + 1 < KT) asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(t), "v"(k));
-            asm volatile("v_min_f64 %0, %0, %1" : "+v"(t) : "v"(k));
-            *e = t;
-            if (i + 1 == KT) kmax = t;
-            k = hi;
-            p = p + 1 == KT ? 0 : p + 1;
+        for (int g = 0; g < KT; g += RG) {
+            double t[RG];
+            double *e[RG];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                e[i] = ring + p * kWave + lane;
+                p = p + 1 == KT ? 0 : p + 1;
+            }
+#pragma unroll
+            for (int i = 0; i < RG; ++i) t[i] = *e[i];
+#pragma unroll
+            for (int i = 0; i < RG; ++i) {
+                double hi = 0.0;
+                if (g + i + 1 < KT) asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(t[i]), "v"(k));
+                asm volatile("v_min_f64 %0, %0, %1" : "+v"(t[i]) : "v"(k));
+                if (g + i + 1 == KT) kmax = t[i];
+                k = hi;
+            }
+#pragma unroll
+            for (int i = 0; i < RG; ++i) *e[i] = t[i];
         }
     }
 };
