@@ -151,6 +151,28 @@ __device__ inline float hit_key_t(double k)
 }
 __device__ inline uint32_t hit_key_gid(double k) { return uint32_t(uint64_t(__double_as_longlong(k))); }
 
+// Sorted insert of k into the ascending keys key[0..N): slot s becomes max(key[s-1],
+// min(key[s], k)) and slot 0 min(key[0], k), each from the old keys, so the 2N operations do
+// not form a chain through a carried key. They are issued from the back, each max two slots
+// behind its min, so no result is read by the next instruction (no wait states). The keys are
+// never NaN, so the min/max are the bare instructions (the generic fmin/fmax would first quiet
+// every key in IEEE mode). OUT: returns max(key[N-1], k), the key pushed out (else kNoHit).
+template <int N, bool OUT>
+__device__ inline double sorted_insert(double (&key)[N], double k)
+{
+    double out = kNoHit;
+    if (OUT) asm volatile("v_max_f64 %0, %1, %2" : "=v"(out) : "v"(key[N - 1]), "v"(k));
+    double t[N];
+#pragma unroll
+    for (int s = N - 1; s >= -1; --s) {
+        if (s >= 0) asm volatile("v_min_f64 %0, %1, %2" : "=v"(t[s]) : "v"(key[s]), "v"(k));
+        const int m = s + 2;  // the slot whose max is due
+        if (m >= 1 && m <= N - 1) asm volatile("v_max_f64 %0, %1, %2" : "=v"(key[m]) : "v"(key[m - 1]), "v"(t[m]));
+    }
+    key[0] = t[0];
+    return out;
+}
+
 template <int K>
 struct HitBuf {
     static constexpr int size = K;
@@ -175,18 +197,7 @@ struct HitBuf {
     // sorted insert of k; the last entry falls off (inserting kNoHit changes nothing). The keys
     // are never NaN, so the min/max are the bare instructions: the generic fmin/fmax would first
     // quiet every loop-carried key (one more v_max_f64 per entry in IEEE mode).
-    __device__ inline void insert(double k)
-    {
-#pragma unroll
-        for (int s = 0; s < K; ++s) {
-            // the max first into a fresh register, then the min in place: the entry keeps its
-            // register and the carried key alternates between two, so no copies are needed
-            double hi = 0.0;
-            if (s + 1 < K) asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
-            asm volatile("v_min_f64 %0, %0, %1" : "+v"(key[s]) : "v"(k));
-            k = hi;
-        }
-    }
+    __device__ inline void insert(double k) { sorted_insert<K, false>(key, k); }
 };
 
 // The same sorted buffer of KR + KT keys with its last KT entries in LDS: a per-wave ring of KT
@@ -233,13 +244,7 @@ struct HitBufTail {
 
     __device__ inline void insert(double k)
     {
-#pragma unroll
-        for (int s = 0; s < KR; ++s) {
-            double hi = 0.0;
-            asm volatile("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(key[s]), "v"(k));
-            asm volatile("v_min_f64 %0, %0, %1" : "+v"(key[s]) : "v"(k));
-            k = hi;
-        }
+        k = sorted_insert<KR, true>(key, k);
         if (!wave_ballot(k != kNoHit)) return;  // every carried key fell into an empty register slot
         // the ring's entries are read RG at a time (their LDS reads in flight together), then
         // passed through the min/max chain and written back
