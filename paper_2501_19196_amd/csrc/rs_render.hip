@@ -836,15 +836,17 @@ __device__ inline void list_append(const ListPool &pool, ListCursor &L, uint32_t
         L.chunk = c;
         L.fill = 0;
     }
+    // The rows are streamed out with nontemporal stores: they are read back only by the adjoint,
+    // after this launch, and the forward's own fetches wait less behind them.
     uint32_t *row = pool.slots + int64_t(L.chunk) * kChunkSlots + L.fill;
     if (entry != kListIdle) {
         const uint32_t below = __builtin_amdgcn_mbcnt_hi(uint32_t(m >> 32), __builtin_amdgcn_mbcnt_lo(uint32_t(m), 0u));
-        row[below] = entry;
+        __builtin_nontemporal_store(entry, row + below);
         if (entry < kListSecond) ++stored;
     }
     if (lane == 0) {
-        row[need - 2] = uint32_t(m);
-        row[need - 1] = uint32_t(m >> 32);
+        __builtin_nontemporal_store(uint32_t(m), row + need - 2);
+        __builtin_nontemporal_store(uint32_t(m >> 32), row + need - 1);
     }
     L.fill += need;
     L.slots += need;
