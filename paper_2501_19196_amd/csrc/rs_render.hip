@@ -875,7 +875,9 @@ constexpr int32_t kDone = INT32_MIN;
 // are, the one the leader lane reaches first (REV: leaves last) is taken and the
 // other pushed (stack entry k lives in lane k of `stackv`). Ordering by the leader
 // lane costs one compare instead of a vote and, in simulation at the scene-scale
-// workload, visits within 0.5 % as many nodes as a majority vote.
+// workload, visits within 0.5 % as many nodes as a majority vote. The loop has one exit (a
+// full stack ends the walk through the same path as an empty one) and decides the
+// two-children case with one scalar compare, which keeps the scalar control flow short.
 template <int OCT, bool COUNT, bool REV>
 __device__ inline int32_t descend(int32_t node, const float4 *__restrict__ nodes, const Slab &sl, uint64_t lead_bit,
                                   float t_lo, float t_hi_w, int lane, int32_t stack_depth, int32_t &sp,
@@ -1103,7 +1105,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
             } else {
                 // While-while traversal: descend internal nodes until a leaf is reached (or the
                 // stack runs dry), then test that leaf; the hit buffer changes only in the leaf step.
-                // The descent is specialised on the wave's direction octant.
+                // The walk is specialised on the wave's direction octant.
                 RS_WALK_BVH()
             }
             if (overflow) {
