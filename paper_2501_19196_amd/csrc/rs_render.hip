@@ -153,10 +153,11 @@ __device__ inline uint32_t hit_key_gid(double k) { return uint32_t(uint64_t(__do
 
 // Sorted insert of k into the ascending keys key[0..N): slot s becomes max(key[s-1],
 // min(key[s], k)) and slot 0 min(key[0], k), each from the old keys, so the 2N operations do
-// not form a chain through a carried key. They are issued from the back, each max two slots
-// behind its min, so no result is read by the next instruction (no wait states). The keys are
-// never NaN, so the min/max are the bare instructions (the generic fmin/fmax would first quiet
-// every key in IEEE mode). OUT: returns max(key[N-1], k), the key pushed out (else kNoHit).
+// not form a chain through a carried key. They are issued from the back, each max three slots
+// behind its min, so a min's result is read five instructions later (f64 results need wait
+// states before they are read; two slots behind left some). The keys are never NaN, so the
+// min/max are the bare instructions (the generic fmin/fmax would first quiet every key in IEEE
+// mode). OUT: returns max(key[N-1], k), the key pushed out (else kNoHit).
 template <int N, bool OUT>
 __device__ inline double sorted_insert(double (&key)[N], double k)
 {
@@ -164,9 +165,9 @@ __device__ inline double sorted_insert(double (&key)[N], double k)
     if (OUT) asm volatile("v_max_f64 %0, %1, %2" : "=v"(out) : "v"(key[N - 1]), "v"(k));
     double t[N];
 #pragma unroll
-    for (int s = N - 1; s >= -1; --s) {
+    for (int s = N - 1; s >= -2; --s) {
         if (s >= 0) asm volatile("v_min_f64 %0, %1, %2" : "=v"(t[s]) : "v"(key[s]), "v"(k));
-        const int m = s + 2;  // the slot whose max is due
+        const int m = s + 3;  // the slot whose max is due
         if (m >= 1 && m <= N - 1) asm volatile("v_max_f64 %0, %1, %2" : "=v"(key[m]) : "v"(key[m - 1]), "v"(t[m]));
     }
     key[0] = t[0];
