@@ -1376,9 +1376,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(waves_for(K,
 __device__ inline void row_seek(const int32_t *__restrict__ prev, const int32_t *__restrict__ fill, int32_t &chunk,
                                 int32_t &start)
 {
+    // wave-uniform addresses, read through the constant address space (scalar loads)
+    typedef const __attribute__((address_space(4))) int32_t *const_i32;
     while (start == 0 && chunk >= 0) {
-        chunk = prev[chunk];
-        start = chunk >= 0 ? fill[chunk] : 0;
+        chunk = ((const_i32)prev)[chunk];
+        start = chunk >= 0 ? ((const_i32)fill)[chunk] : 0;
     }
 }
 
@@ -1388,7 +1390,11 @@ __device__ inline uint32_t row_entry(const uint32_t *__restrict__ slots, int32_t
                                      int lane)
 {
     const uint32_t *row_end = slots + int64_t(chunk) * kChunkSlots + start;
-    const uint64_t m = uint64_t(row_end[-2]) | (uint64_t(row_end[-1]) << 32);
+    // the mask's address is wave-uniform: read it through the constant address space, so it is
+    // a scalar load (the pool is only read by this kernel)
+    typedef const __attribute__((address_space(4))) uint32_t *const_u32;
+    const const_u32 mend = (const_u32)(row_end - 2);
+    const uint64_t m = uint64_t(mend[0]) | (uint64_t(mend[1]) << 32);
     const int32_t k = __popcll(m);
     start -= k + 2;
     const bool mine = ((m >> lane) & 1ull) != 0;
